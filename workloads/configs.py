@@ -1,0 +1,97 @@
+"""The five workloads (lattice, direction matrix, sizes) the project is built around.
+
+Lattices and splines are the ones of the paper's Table 1 (BCC linear rhombic
+dodecahedron, the Cartesian truncated rhombic dodecahedron / ZP element, the
+BCC quartic truncated rhombic dodecahedron, the FCC 6-direction truncated
+octahedron) plus a 4-D spline on the D4* lattice in the spirit of Sec. 5.2.
+
+Coefficient storage: coset k is an s-D array indexed by i (x fastest) holding
+the value at lattice site D i + l_k; shifts are ordered by sum_a l_a D^a.
+``lo``/``hi`` bound the queries so that every query's full support lies in
+the stored arrays (the largest first stored coordinate over the cosets plus
+the support half-width, and symmetrically at the top).
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+I3 = np.eye(3, dtype=np.int64)
+BCC_DIAG = np.array([[-1, 1, 1, -1],
+                     [1, -1, 1, -1],
+                     [1, 1, -1, -1]], dtype=np.int64)          # the four BCC diagonals
+HAD4 = np.array([[1, 1, 1, 1],
+                 [1, 1, -1, -1],
+                 [1, -1, 1, -1],
+                 [1, -1, -1, 1]], dtype=np.int64).T            # Hadamard directions
+
+L_CC = I3
+L_BCC = np.array([[-1, 1, 1], [1, -1, 1], [1, 1, -1]], dtype=np.int64)
+L_FCC = np.array([[0, 1, 1], [1, 0, 1], [1, 1, 0]], dtype=np.int64)
+# D4* realised as 2Z^4 u (2Z^4 + (1,1,1,1)): columns 2e_1, 2e_2, 2e_3, (1,1,1,1)
+L_D4S = np.array([[2, 0, 0, 1], [0, 2, 0, 1], [0, 0, 2, 1], [0, 0, 0, 1]], dtype=np.int64)
+# the paper's D4 generating matrix (Sec. 5.2)
+L_D4 = np.array([[-1, 0, 0, 0], [1, 0, -1, -1], [0, -1, 0, 1], [0, -1, 1, 0]], dtype=np.int64)
+
+XI_BCC_LINEAR = BCC_DIAG
+XI_ZP = np.hstack([I3, BCC_DIAG])
+XI_BCC_QUARTIC = np.hstack([2 * I3, BCC_DIAG])
+XI_FCC6 = np.array([[1, -1, 1, 1, 0, 0],
+                    [1, 1, 0, 0, 1, -1],
+                    [0, 0, 1, -1, 1, 1]], dtype=np.int64)
+XI_D4S8 = np.hstack([2 * np.eye(4, dtype=np.int64), HAD4])
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    title: str
+    L: np.ndarray
+    Xi: np.ndarray
+    D: int
+    shifts: tuple          # coset shifts l_k
+    dims: tuple            # per-coset array dims (n_0, ..., n_{s-1})
+    n_queries: int
+    lo: float
+    hi: float
+    coeff_kind: str        # 'uniform' or 'field'
+    noise: float = 0.0
+    passes: str = "fwd"    # 'fwd', 'fwd+grad', 'mse'
+    lookups: int = 0       # sites with nonzero weight per query (Table 1 column)
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def s(self):
+        return self.Xi.shape[0]
+
+    @property
+    def M(self):
+        return len(self.shifts)
+
+
+def _z(s):
+    return (0,) * s
+
+
+CONFIGS = {
+    "c1": Config("c1", "BCC 2x32^3, linear rhombic dodecahedron (4 dir.), FP64 coefficients, 1e5 queries, forward",
+                 L_BCC, XI_BCC_LINEAR, 2, (_z(3), (1, 1, 1)), (32, 32, 32), 100000, 3.0, 60.0,
+                 "uniform", lookups=4, extra={"coeff_dtype": "f64"}),
+    "c2": Config("c2", "Z^3 256^3, 7-direction ZP box spline, FP32, 2^24 random queries, forward",
+                 L_CC, XI_ZP, 1, (_z(3),), (256, 256, 256), 1 << 24, 2.5, 252.5,
+                 "field", noise=0.01, lookups=53),
+    "c3": Config("c3", "BCC 2x192^3, quartic 7-direction box spline, 1024^2 rays x 512 steps, forward + grad",
+                 L_BCC, XI_BCC_QUARTIC, 2, (_z(3), (1, 1, 1)), (192, 192, 192), 1 << 29, 4.0, 379.0,
+                 "field", noise=0.01, passes="fwd+grad", lookups=30,
+                 extra={"rays": (1024, 1024), "steps": 512}),
+    "c4": Config("c4", "FCC 4x128^3, 6-direction box spline, 2^22 queries, MSE forward + backward",
+                 L_FCC, XI_FCC6, 2, (_z(3), (1, 1, 0), (1, 0, 1), (0, 1, 1)), (128, 128, 128), 1 << 22,
+                 3.0, 252.0, "field", passes="mse", lookups=16),
+    "c5": Config("c5", "D4* 2x48^4, 8-direction box spline, 2^22 queries, forward + backward",
+                 L_D4S, XI_D4S8, 2, (_z(4), (1, 1, 1, 1)), (48, 48, 48, 48), 1 << 22, 4.0, 91.0,
+                 "field", passes="mse", lookups=60),
+}
+
+
+def get(name):
+    return CONFIGS[name]
