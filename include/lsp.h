@@ -1,0 +1,140 @@
+/*
+ * lsp.h -- C ABI of the lattice box-spline evaluation library (gfx950).
+ *
+ * The library evaluates the lattice convolution sum
+ *
+ *     f(x) = sum_{n in L Z^s} c_n phi(x - n),    phi(w) = |det L| M_Xi(w + c0),
+ *
+ * (Horacsek & Alim, "Automatic Generation of Interpolants for Lattice
+ * Samplings: Part I", Eq. conv_sum with h = 1) for a box spline M_Xi (Sec. 3,
+ * box-spline definition) centred at the origin (c0 = half the sum of the
+ * directions) and scaled to a partition of unity on the lattice (the
+ * requirement on phi stated in Sec. 4.1), at many query points, with the
+ * paper's fast scheme (Sec. 4, Algorithm 1).  It also gives the spatial
+ * gradient, the adjoint (transpose) of c -> f, a mean-squared-error head and
+ * a ray-marching sample generator.
+ *
+ * Conventions
+ *  - Status: every function returns lsp_status (0 = LSP_OK, < 0 error); no
+ *    exception or abort crosses the ABI.  lsp_status_string() describes a code.
+ *  - Lattice storage (Sec. 4.1, Cartesian coset decomposition GL = D I): the
+ *    lattice is the union of M cosets D Z^s + l_k, D the smallest positive
+ *    integer with D Z^s inside L Z^s, shifts l_k in [0, D)^s ordered by
+ *    sum_a l_a D^a (l_0 = 0).  Coset k is an s-D array; element i (x index
+ *    fastest) holds c at the lattice site D i + l_k.  Sites outside the
+ *    stored arrays have c = 0 (zero extension).
+ *  - Queries: N x s float32, row-major, world coordinates (h = 1).  NaN or
+ *    infinite queries yield NaN outputs and never read out of bounds.
+ *  - Memory: all data pointers are device pointers owned by the caller and
+ *    must stay valid until the work queued on the stream completes.  Plans
+ *    own their host tables only.  No entry point allocates device memory or
+ *    synchronises; all work is queued on `stream` (a hipStream_t, NULL for
+ *    the default stream).
+ *  - Supported splines: the library ships generated tables for a fixed set
+ *    of (lattice, direction matrix) pairs (lsp_plan_create matches L by its
+ *    coset structure and Xi up to column order and column signs).
+ */
+#ifndef LSP_H
+#define LSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lsp_status;
+#define LSP_OK 0
+#define LSP_ERR_NULL (-1)          /* a required pointer is NULL */
+#define LSP_ERR_INVALID (-2)       /* malformed argument (sizes, rank, lattice) */
+#define LSP_ERR_UNSUPPORTED (-3)   /* no generated tables for this (L, Xi) */
+#define LSP_ERR_DTYPE (-4)         /* unknown or mismatched dtype */
+#define LSP_ERR_DIMS (-5)          /* coefficient dims out of range */
+#define LSP_ERR_HIP (-6)           /* a HIP runtime call failed */
+#define LSP_ERR_NOT_ON_LATTICE (-7)/* a direction of Xi is not a lattice vector */
+
+/* coefficient storage types */
+#define LSP_F32 0
+#define LSP_BF16 1   /* bfloat16 (upper half of an IEEE float32) */
+#define LSP_F16 2    /* IEEE half */
+#define LSP_F64 3    /* float64: evaluation then runs in FP64 (accuracy check) */
+
+typedef struct lsp_plan_s* lsp_plan;
+typedef struct lsp_vol_s* lsp_vol;
+
+typedef struct {
+  int32_t s;                /* dimension */
+  int32_t n_dirs;           /* directions in Xi */
+  int32_t det_l;            /* |det L| */
+  int32_t D;                /* coset sub-lattice spacing */
+  int32_t n_cosets;         /* M */
+  int32_t shifts[8][4];     /* coset shifts l_k */
+  int32_t degree;           /* polynomial degree of the pieces (n - s) */
+  int32_t n_subregions;     /* K: non-equivalent sub-regions after the fold */
+  int32_t n_planes;         /* Q: splitting planes inside the fold chamber */
+  int32_t fold_even;        /* 1 if the fold group is the even-sign subgroup */
+  int32_t stencil[16];      /* sites gathered per coset, per sub-region */
+  int32_t lookups;          /* sites with nonzero weight per query (Table 1) */
+  int32_t n_monomials;      /* monomials per polynomial piece */
+  int32_t nnz[16];          /* nonzero polynomial coefficients per sub-region */
+  int32_t offset_min;       /* per-axis site offset range around the cell */
+  int32_t offset_max;
+  char name[32];            /* spline name */
+} lsp_info;
+
+/* Create a plan for lattice L (s x s, row-major; columns generate the lattice)
+ * and direction matrix Xi (s x n, row-major; columns are the directions),
+ * s in {3, 4}.  Errors: LSP_ERR_NULL, LSP_ERR_INVALID (singular L, n < s),
+ * LSP_ERR_NOT_ON_LATTICE (a direction outside L Z^s, so phi would not be a
+ * partition of unity), LSP_ERR_UNSUPPORTED.  flags: reserved, pass 0. */
+lsp_status lsp_plan_create(int32_t s, const int32_t* L, int32_t n, const int32_t* Xi, uint32_t flags,
+                           lsp_plan* out);
+lsp_status lsp_plan_info(lsp_plan plan, lsp_info* out);
+lsp_status lsp_plan_destroy(lsp_plan plan);
+
+/* Bind M device arrays (one per coset, in shift order) of dtype `dtype` and
+ * dims[0..s-1] (x first; same for every coset; each dim in [1, 2^20], total
+ * elements below 2^31).  The view is non-owning. */
+lsp_status lsp_vol_bind(lsp_plan plan, int32_t dtype, const void* const* coset_ptrs, const int64_t* dims,
+                        lsp_vol* out);
+lsp_status lsp_vol_release(lsp_vol vol);
+
+/* Forward (Algorithm 1): f[q] for N queries x (device, N x s float32).  f and
+ * grad_x are float32, or float64 when the volume is LSP_F64.  grad_x (N x s,
+ * row-major) may be NULL; otherwise it receives the spatial gradient of f. */
+lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* f, void* grad_x,
+                    void* stream);
+
+/* Forward with a mean-squared-error head against targets y (N float32):
+ * writes f, dL/df = 2 (f - y) / N, and adds L = sum (f - y)^2 / N to *loss
+ * (float64; the caller zeroes it).  Float32 volumes only. */
+lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n, float* f,
+                        float* dloss_df, double* loss, void* stream);
+
+/* Adjoint: for upstream gradients g (N float32) adds sum_q g_q phi(x_q - site)
+ * into grad_c (M float32 device arrays shaped like the volume; the caller
+ * zeroes them; FP32 atomics, so the summation order is not deterministic)
+ * and, if grad_x is not NULL, writes grad_x[q] = g_q * grad f(x_q) (N x s).
+ * Float32/bf16/f16 volumes. */
+lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
+                            float* const* grad_c, float* grad_x, void* stream);
+
+/* Ray-marched samples (3-D only): ray r in [ray0, ray0 + nrays) covers pixel
+ * (u, v) in 8x8 tiles (tile = r / 64 in row-major tile order, within-tile
+ * index r % 64 = (v % 8) * 8 + u % 8) of a W x H image; its samples are
+ *   p_j = c + A ((2u+1)/W - 1, (2v+1)/H - 1, (2j+1)/steps - 1),  j < steps,
+ * every product and sum rounded to float32 (no fused multiply-add).  Writes
+ * per ray (sum_j f, sum_j grad f) as 4 floats to out (nrays x 4); if samples
+ * is not NULL also every sample's (f, grad f) (nrays x steps x 4).
+ * W and H multiples of 8; c[3], A[9] row-major host arrays. */
+lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
+                         int32_t steps, int64_t ray0, int64_t nrays, float* out, float* samples, void* stream);
+
+const char* lsp_status_string(lsp_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSP_H */

@@ -1,0 +1,122 @@
+"""Object layer over the C ABI for torch device tensors."""
+
+import torch
+
+from . import _lib as L
+
+_DTYPES = {torch.float32: L.LSP_F32, torch.bfloat16: L.LSP_BF16, torch.float16: L.LSP_F16,
+           torch.float64: L.LSP_F64}
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _require_device(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU")
+        if t is not None and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+
+
+class Volume:
+    """Coefficient arrays bound to a plan: M device tensors of shape
+    (n_{s-1}, ..., n_0) (x fastest), one per coset, same dtype."""
+
+    def __init__(self, spline, coeffs):
+        coeffs = list(coeffs)
+        if len(coeffs) != spline.info["n_cosets"]:
+            raise ValueError(f"expected {spline.info['n_cosets']} coset arrays")
+        _require_device(*coeffs)
+        dt = coeffs[0].dtype
+        if dt not in _DTYPES or any(c.dtype != dt or c.shape != coeffs[0].shape for c in coeffs):
+            raise ValueError("coset arrays must share shape and a supported dtype")
+        if coeffs[0].dim() != spline.s:
+            raise ValueError("coset arrays must be s-dimensional")
+        self.spline = spline
+        self.coeffs = coeffs              # keeps the memory alive
+        self.dtype = dt
+        self.dims = tuple(reversed(coeffs[0].shape))
+        self.handle = L.lsp_vol_bind(spline.plan, _DTYPES[dt], [c.data_ptr() for c in coeffs], self.dims)
+
+    @property
+    def out_dtype(self):
+        return torch.float64 if self.dtype == torch.float64 else torch.float32
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                L.lsp_vol_release(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+class LatticeSpline:
+    """A plan for lattice L and direction matrix Xi (generated tables must exist)."""
+
+    def __init__(self, L_matrix, Xi):
+        self.plan = L.lsp_plan_create(L_matrix, Xi)
+        self.info = L.lsp_plan_info(self.plan)
+        self.s = self.info["s"]
+
+    def __del__(self):
+        p = getattr(self, "plan", None)
+        if p is not None and p.value:
+            try:
+                L.lsp_plan_destroy(p)
+            except Exception:
+                pass
+            self.plan = None
+
+    def bind(self, coeffs):
+        return Volume(self, coeffs)
+
+    # ------------------------------------------------------------- forward
+    def eval(self, vol, x, grad=False, out=None, grad_out=None):
+        _require_device(x)
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != self.s:
+            raise ValueError("x must be an N x s float32 tensor")
+        n = x.shape[0]
+        f = out if out is not None else torch.empty(n, device=x.device, dtype=vol.out_dtype)
+        g = None
+        if grad:
+            g = grad_out if grad_out is not None else torch.empty(n, self.s, device=x.device, dtype=vol.out_dtype)
+        L.lsp_eval(self.plan, vol.handle, x.data_ptr(), n, f.data_ptr(), _ptr(g), _stream())
+        return (f, g) if grad else f
+
+    def eval_mse(self, vol, x, y):
+        _require_device(x, y)
+        n = x.shape[0]
+        f = torch.empty(n, device=x.device, dtype=torch.float32)
+        dldf = torch.empty(n, device=x.device, dtype=torch.float32)
+        loss = torch.zeros(1, device=x.device, dtype=torch.float64)
+        L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(), dldf.data_ptr(),
+                       loss.data_ptr(), _stream())
+        return f, dldf, loss
+
+    def adjoint(self, vol, x, g, grad_x=False, grad_c=None):
+        """grad_c (zero-initialised here unless given) += A^T g; grad_x = g * grad f."""
+        _require_device(x, g)
+        n = x.shape[0]
+        if grad_c is None:
+            grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
+        gx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
+        L.lsp_eval_adjoint(self.plan, vol.handle, x.data_ptr(), g.data_ptr(), n, [t.data_ptr() for t in grad_c],
+                           _ptr(gx), _stream())
+        return grad_c, gx
+
+    def rays(self, vol, centre, A, W, H, steps, ray0=0, nrays=None, samples=False):
+        nrays = W * H - ray0 if nrays is None else nrays
+        dev = vol.coeffs[0].device
+        out = torch.empty(nrays, 4, device=dev, dtype=torch.float32)
+        smp = torch.empty(nrays, steps, 4, device=dev, dtype=torch.float32) if samples else None
+        L.lsp_eval_rays(self.plan, vol.handle, list(centre), [float(v) for row in A for v in row], W, H, steps,
+                        ray0, nrays, out.data_ptr(), _ptr(smp), _stream())
+        return (out, smp) if samples else out

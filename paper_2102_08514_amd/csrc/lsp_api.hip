@@ -1,0 +1,453 @@
+// Host side of the C ABI declared in include/lsp.h: plan matching, argument
+// validation and kernel dispatch.  All launches are asynchronous on the
+// caller's stream; nothing here allocates device memory.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lsp.h"
+#include "lsp_kernels.hip"
+
+namespace {
+
+using namespace lsp;
+
+enum SpecId { kBccLinear = 0, kCcZp, kBccQuartic, kFcc6, kD4s8, kNumSpecs };
+
+struct SpecDesc {
+  const char* name;
+  int s, ndir, D, M, det, deg, K, Q, fold_even, nmon, omin, omax;
+  std::vector<std::vector<int>> dirs;
+  std::vector<std::vector<int>> shifts;
+  std::vector<int> nsite, nnz;
+  int lookups;
+};
+
+template <class SP>
+SpecDesc describe(const char* name) {
+  SpecDesc d{};
+  d.name = name;
+  d.s = SP::S; d.ndir = SP::NDIR; d.D = SP::D; d.M = SP::M; d.det = SP::DETL; d.deg = SP::DEG;
+  d.K = SP::K; d.Q = SP::Q; d.fold_even = SP::FOLD_D ? 1 : 0; d.nmon = SP::NMON;
+  d.omin = SP::OMIN; d.omax = SP::OMAX;
+  for (int j = 0; j < SP::NDIR; ++j) d.dirs.emplace_back(SP::XI[j], SP::XI[j] + SP::S);
+  for (int k = 0; k < SP::M; ++k) d.shifts.emplace_back(SP::SHIFT[k], SP::SHIFT[k] + SP::S);
+  for (int k = 0; k < SP::K; ++k) { d.nsite.push_back(SP::NSITE[k]); d.nnz.push_back(SP::NNZ[k]); }
+  return d;
+}
+
+const std::vector<SpecDesc>& specs() {
+  static const std::vector<SpecDesc> all = {
+      describe<SplineBccLinear>("bcc_linear"), describe<SplineCcZp>("cc_zp"),
+      describe<SplineBccQuartic>("bcc_quartic"), describe<SplineFcc6>("fcc_6dir"),
+      describe<SplineD4s8>("d4s_8dir")};
+  return all;
+}
+
+}  // namespace
+
+struct lsp_plan_s {
+  int spec;
+};
+
+struct lsp_vol_s {
+  int spec;
+  int dtype;
+  Vol vol;
+  int64_t total;
+};
+
+namespace {
+
+// exact small-integer linear algebra on the host
+long long det_int(const std::vector<std::vector<long long>>& A) {
+  const int n = static_cast<int>(A.size());
+  if (n == 1) return A[0][0];
+  long long det = 0;
+  for (int c = 0; c < n; ++c) {
+    std::vector<std::vector<long long>> m;
+    for (int r = 1; r < n; ++r) {
+      std::vector<long long> row;
+      for (int cc = 0; cc < n; ++cc)
+        if (cc != c) row.push_back(A[r][cc]);
+      m.push_back(row);
+    }
+    det += ((c & 1) ? -1 : 1) * A[0][c] * det_int(m);
+  }
+  return det;
+}
+
+// adjugate: adj(A) A = det(A) I
+std::vector<std::vector<long long>> adj_int(const std::vector<std::vector<long long>>& A) {
+  const int n = static_cast<int>(A.size());
+  std::vector<std::vector<long long>> adj(n, std::vector<long long>(n, 1));
+  if (n == 1) return adj;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      std::vector<std::vector<long long>> m;
+      for (int r = 0; r < n; ++r) {
+        if (r == i) continue;
+        std::vector<long long> row;
+        for (int c = 0; c < n; ++c)
+          if (c != j) row.push_back(A[r][c]);
+        m.push_back(row);
+      }
+      adj[j][i] = (((i + j) & 1) ? -1 : 1) * det_int(m);
+    }
+  return adj;
+}
+
+long long gcdll(long long a, long long b) {
+  a = a < 0 ? -a : a;
+  b = b < 0 ? -b : b;
+  while (b) { long long t = a % b; a = b; b = t; }
+  return a;
+}
+
+bool on_lattice(const std::vector<std::vector<long long>>& adj, long long det, const std::vector<long long>& v) {
+  const int n = static_cast<int>(v.size());
+  for (int i = 0; i < n; ++i) {
+    long long acc = 0;
+    for (int j = 0; j < n; ++j) acc += adj[i][j] * v[j];
+    if (acc % det != 0) return false;
+  }
+  return true;
+}
+
+std::vector<int> canon_dir(std::vector<int> v) {
+  std::vector<int> neg(v.size());
+  for (size_t i = 0; i < v.size(); ++i) neg[i] = -v[i];
+  return std::max(v, neg);
+}
+
+template <class SP, class CT, class AT>
+lsp_status launch_eval(const lsp_vol_s* v, const float* x, int64_t n, void* f, void* grad, hipStream_t st) {
+  const int block = 256;
+  const long long grid = (n + block - 1) / block;
+  if (grad)
+    hipLaunchKernelGGL((k_eval<SP, CT, AT, true>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, x,
+                       static_cast<long long>(n), static_cast<AT*>(f), static_cast<AT*>(grad));
+  else
+    hipLaunchKernelGGL((k_eval<SP, CT, AT, false>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, x,
+                       static_cast<long long>(n), static_cast<AT*>(f), static_cast<AT*>(grad));
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+template <class SP>
+lsp_status eval_spec(const lsp_vol_s* v, const float* x, int64_t n, void* f, void* grad, hipStream_t st) {
+  switch (v->dtype) {
+    case LSP_F32: return launch_eval<SP, float, float>(v, x, n, f, grad, st);
+    case LSP_BF16: return launch_eval<SP, bf16_t, float>(v, x, n, f, grad, st);
+    case LSP_F16: return launch_eval<SP, f16_t, float>(v, x, n, f, grad, st);
+    case LSP_F64: return launch_eval<SP, double, double>(v, x, n, f, grad, st);
+  }
+  return LSP_ERR_DTYPE;
+}
+
+template <class SP, class CT>
+lsp_status launch_mse(const lsp_vol_s* v, const float* x, const float* y, int64_t n, float* f, float* dldf,
+                      double* loss, hipStream_t st) {
+  const int block = 256;
+  const long long grid = (n + block - 1) / block;
+  hipLaunchKernelGGL((k_eval_mse<SP, CT>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, x, y,
+                     static_cast<long long>(n), 1.0f / static_cast<float>(n), f, dldf, loss);
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+template <class SP>
+lsp_status mse_spec(const lsp_vol_s* v, const float* x, const float* y, int64_t n, float* f, float* dldf,
+                    double* loss, hipStream_t st) {
+  switch (v->dtype) {
+    case LSP_F32: return launch_mse<SP, float>(v, x, y, n, f, dldf, loss, st);
+    case LSP_BF16: return launch_mse<SP, bf16_t>(v, x, y, n, f, dldf, loss, st);
+    case LSP_F16: return launch_mse<SP, f16_t>(v, x, y, n, f, dldf, loss, st);
+  }
+  return LSP_ERR_DTYPE;
+}
+
+template <class SP, class CT>
+lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_t n, float* const* grad_c,
+                      float* grad_x, hipStream_t st) {
+  GradVol gv{};
+  for (int k = 0; k < SP::M; ++k) gv.base[k] = grad_c[k];
+  const int block = 256;
+  const long long grid = (n + block - 1) / block;
+  if (grad_x)
+    hipLaunchKernelGGL((k_adjoint<SP, CT, true>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, gv,
+                       x, g, static_cast<long long>(n), grad_x);
+  else
+    hipLaunchKernelGGL((k_adjoint<SP, CT, false>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol,
+                       gv, x, g, static_cast<long long>(n), grad_x);
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+template <class SP>
+lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t n, float* const* grad_c,
+                    float* grad_x, hipStream_t st) {
+  switch (v->dtype) {
+    case LSP_F32: return launch_adj<SP, float>(v, x, g, n, grad_c, grad_x, st);
+    case LSP_BF16: return launch_adj<SP, bf16_t>(v, x, g, n, grad_c, grad_x, st);
+    case LSP_F16: return launch_adj<SP, f16_t>(v, x, g, n, grad_c, grad_x, st);
+  }
+  return LSP_ERR_DTYPE;
+}
+
+template <class SP, class CT>
+lsp_status launch_rays(const lsp_vol_s* v, const RayParams& rp, int64_t ray0, int64_t nrays, float* out,
+                       float* samples, hipStream_t st) {
+  const int block = 256;
+  const long long grid = (nrays + block - 1) / block;
+  hipLaunchKernelGGL((k_rays<SP, CT>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, rp,
+                     static_cast<long long>(ray0), static_cast<long long>(nrays), out, samples);
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+template <class SP>
+lsp_status rays_spec(const lsp_vol_s* v, const RayParams& rp, int64_t ray0, int64_t nrays, float* out,
+                     float* samples, hipStream_t st) {
+  if constexpr (SP::S != 3) {
+    return LSP_ERR_UNSUPPORTED;
+  } else {
+    switch (v->dtype) {
+      case LSP_F32: return launch_rays<SP, float>(v, rp, ray0, nrays, out, samples, st);
+      case LSP_BF16: return launch_rays<SP, bf16_t>(v, rp, ray0, nrays, out, samples, st);
+      case LSP_F16: return launch_rays<SP, f16_t>(v, rp, ray0, nrays, out, samples, st);
+    }
+    return LSP_ERR_DTYPE;
+  }
+}
+
+#define LSP_DISPATCH(spec, FN, ...)                        \
+  switch (spec) {                                          \
+    case kBccLinear: return FN<SplineBccLinear>(__VA_ARGS__); \
+    case kCcZp: return FN<SplineCcZp>(__VA_ARGS__);           \
+    case kBccQuartic: return FN<SplineBccQuartic>(__VA_ARGS__); \
+    case kFcc6: return FN<SplineFcc6>(__VA_ARGS__);           \
+    case kD4s8: return FN<SplineD4s8>(__VA_ARGS__);           \
+  }                                                        \
+  return LSP_ERR_UNSUPPORTED;
+
+}  // namespace
+
+extern "C" {
+
+const char* lsp_status_string(lsp_status s) {
+  switch (s) {
+    case LSP_OK: return "ok";
+    case LSP_ERR_NULL: return "a required pointer is NULL";
+    case LSP_ERR_INVALID: return "invalid argument";
+    case LSP_ERR_UNSUPPORTED: return "no generated tables for this lattice / direction matrix";
+    case LSP_ERR_DTYPE: return "unsupported or mismatched coefficient dtype";
+    case LSP_ERR_DIMS: return "coefficient dims out of range";
+    case LSP_ERR_HIP: return "HIP runtime error";
+    case LSP_ERR_NOT_ON_LATTICE: return "a direction of Xi is not a lattice vector";
+  }
+  return "unknown status";
+}
+
+lsp_status lsp_plan_create(int32_t s, const int32_t* L, int32_t n, const int32_t* Xi, uint32_t flags,
+                           lsp_plan* out) {
+  (void)flags;
+  if (!L || !Xi || !out) return LSP_ERR_NULL;
+  *out = nullptr;
+  if (s < 1 || s > 4 || n < s || n > 16) return LSP_ERR_INVALID;
+  std::vector<std::vector<long long>> A(s, std::vector<long long>(s));
+  for (int r = 0; r < s; ++r)
+    for (int c = 0; c < s; ++c) A[r][c] = L[r * s + c];
+  const long long det = det_int(A);
+  if (det == 0) return LSP_ERR_INVALID;
+  const auto adj = adj_int(A);  // L^{-1} = adj / det
+  // D: smallest positive integer with D L^{-1} integral
+  long long g = det;
+  for (auto& row : adj)
+    for (long long v : row) g = gcdll(g, v);
+  const long long D = (det < 0 ? -det : det) / g;
+  std::vector<std::vector<int>> dirs;
+  for (int j = 0; j < n; ++j) {
+    std::vector<long long> v(s);
+    std::vector<int> vi(s);
+    for (int a = 0; a < s; ++a) { v[a] = Xi[a * n + j]; vi[a] = Xi[a * n + j]; }
+    if (!on_lattice(adj, det, v)) return LSP_ERR_NOT_ON_LATTICE;
+    dirs.push_back(canon_dir(vi));
+  }
+  // rank of Xi must be s
+  {
+    bool spans = false;
+    std::vector<int> idx(s);
+    // try all s-subsets of columns for a nonzero determinant
+    std::vector<int> sel(n, 0);
+    std::fill(sel.begin(), sel.begin() + s, 1);
+    std::sort(sel.begin(), sel.end(), std::greater<int>());
+    do {
+      std::vector<std::vector<long long>> B(s, std::vector<long long>(s));
+      int c = 0;
+      for (int j = 0; j < n; ++j)
+        if (sel[j]) {
+          for (int a = 0; a < s; ++a) B[a][c] = Xi[a * n + j];
+          ++c;
+        }
+      if (det_int(B) != 0) { spans = true; break; }
+    } while (std::prev_permutation(sel.begin(), sel.end()));
+    if (!spans) return LSP_ERR_INVALID;
+  }
+  std::sort(dirs.begin(), dirs.end());
+  // coset shifts of L Z^s in [0, D)^s
+  std::vector<std::vector<int>> shifts;
+  {
+    std::vector<long long> v(s, 0);
+    long long total = 1;
+    for (int a = 0; a < s; ++a) total *= D;
+    for (long long code = 0; code < total; ++code) {
+      long long c = code;
+      std::vector<int> vi(s);
+      for (int a = 0; a < s; ++a) { v[a] = c % D; vi[a] = static_cast<int>(v[a]); c /= D; }
+      if (on_lattice(adj, det, v)) shifts.push_back(vi);
+    }
+  }
+  for (int id = 0; id < kNumSpecs; ++id) {
+    const SpecDesc& sd = specs()[id];
+    if (sd.s != s || sd.ndir != n || sd.D != D || sd.M != static_cast<int>(shifts.size())) continue;
+    std::vector<std::vector<int>> sdirs;
+    for (auto& dv : sd.dirs) sdirs.push_back(canon_dir(dv));
+    std::sort(sdirs.begin(), sdirs.end());
+    if (sdirs != dirs) continue;
+    if (sd.shifts != shifts) continue;
+    lsp_plan p = new (std::nothrow) lsp_plan_s;
+    if (!p) return LSP_ERR_INVALID;
+    p->spec = id;
+    *out = p;
+    return LSP_OK;
+  }
+  return LSP_ERR_UNSUPPORTED;
+}
+
+lsp_status lsp_plan_info(lsp_plan plan, lsp_info* out) {
+  if (!plan || !out) return LSP_ERR_NULL;
+  std::memset(out, 0, sizeof(*out));
+  const SpecDesc& sd = specs()[plan->spec];
+  out->s = sd.s; out->n_dirs = sd.ndir; out->det_l = sd.det; out->D = sd.D; out->n_cosets = sd.M;
+  for (int k = 0; k < sd.M; ++k)
+    for (int a = 0; a < sd.s; ++a) out->shifts[k][a] = sd.shifts[k][a];
+  out->degree = sd.deg; out->n_subregions = sd.K; out->n_planes = sd.Q; out->fold_even = sd.fold_even;
+  for (int k = 0; k < sd.K && k < 16; ++k) { out->stencil[k] = sd.nsite[k]; out->nnz[k] = sd.nnz[k]; }
+  // every query gathers the same total over its cosets when K = 1; report the
+  // sub-region-averaged total otherwise
+  long long tot = 0;
+  for (int v : sd.nsite) tot += v;
+  out->lookups = static_cast<int32_t>((tot * sd.M + sd.K / 2) / sd.K);
+  out->n_monomials = sd.nmon;
+  out->offset_min = sd.omin; out->offset_max = sd.omax;
+  std::strncpy(out->name, sd.name, sizeof(out->name) - 1);
+  return LSP_OK;
+}
+
+lsp_status lsp_plan_destroy(lsp_plan plan) {
+  if (!plan) return LSP_ERR_NULL;
+  delete plan;
+  return LSP_OK;
+}
+
+lsp_status lsp_vol_bind(lsp_plan plan, int32_t dtype, const void* const* coset_ptrs, const int64_t* dims,
+                        lsp_vol* out) {
+  if (!plan || !coset_ptrs || !dims || !out) return LSP_ERR_NULL;
+  *out = nullptr;
+  if (dtype < LSP_F32 || dtype > LSP_F64) return LSP_ERR_DTYPE;
+  const SpecDesc& sd = specs()[plan->spec];
+  lsp_vol v = new (std::nothrow) lsp_vol_s;
+  if (!v) return LSP_ERR_INVALID;
+  std::memset(&v->vol, 0, sizeof(v->vol));
+  int64_t total = 1;
+  for (int a = 0; a < sd.s; ++a) {
+    if (dims[a] < 1 || dims[a] > (1 << 20)) { delete v; return LSP_ERR_DIMS; }
+    v->vol.stride[a] = static_cast<int>(total);
+    v->vol.dims[a] = static_cast<int>(dims[a]);
+    total *= dims[a];
+    if (total >= (int64_t(1) << 31)) { delete v; return LSP_ERR_DIMS; }
+  }
+  for (int k = 0; k < sd.M; ++k) {
+    if (!coset_ptrs[k]) { delete v; return LSP_ERR_NULL; }
+    v->vol.base[k] = coset_ptrs[k];
+  }
+  v->spec = plan->spec;
+  v->dtype = dtype;
+  v->total = total;
+  *out = v;
+  return LSP_OK;
+}
+
+lsp_status lsp_vol_release(lsp_vol vol) {
+  if (!vol) return LSP_ERR_NULL;
+  delete vol;
+  return LSP_OK;
+}
+
+static lsp_status check_pv(lsp_plan plan, lsp_vol vol) {
+  if (!plan || !vol) return LSP_ERR_NULL;
+  if (plan->spec != vol->spec) return LSP_ERR_INVALID;
+  return LSP_OK;
+}
+
+lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* f, void* grad_x, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if (n == 0) return LSP_OK;
+  if (!x || !f) return LSP_ERR_NULL;
+  if (n > (int64_t(1) << 40)) return LSP_ERR_INVALID;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, eval_spec, vol, x, n, f, grad_x, s)
+}
+
+lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n, float* f,
+                        float* dloss_df, double* loss, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if (n == 0) return LSP_OK;
+  if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, f, dloss_df, loss, s)
+}
+
+lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
+                            float* const* grad_c, float* grad_x, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if (n == 0) return LSP_OK;
+  if (!x || !g || !grad_c) return LSP_ERR_NULL;
+  const SpecDesc& sd = specs()[plan->spec];
+  for (int k = 0; k < sd.M; ++k)
+    if (!grad_c[k]) return LSP_ERR_NULL;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, grad_c, grad_x, s)
+}
+
+lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
+                         int32_t steps, int64_t ray0, int64_t nrays, float* out, float* samples, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (!c || !A) return LSP_ERR_NULL;
+  if (W <= 0 || H <= 0 || (W & 7) || (H & 7) || steps <= 0 || ray0 < 0 || nrays < 0 ||
+      ray0 + nrays > static_cast<int64_t>(W) * H)
+    return LSP_ERR_INVALID;
+  if (nrays == 0) return LSP_OK;
+  if (!out) return LSP_ERR_NULL;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  RayParams rp{};
+  for (int a = 0; a < 3; ++a) rp.c[a] = c[a];
+  for (int a = 0; a < 9; ++a) rp.A[a] = A[a];
+  rp.W = W; rp.H = H; rp.steps = steps;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, rays_spec, vol, rp, ray0, nrays, out, samples, s)
+}
+
+}  // extern "C"

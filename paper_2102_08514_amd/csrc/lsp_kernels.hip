@@ -1,0 +1,441 @@
+// HIP kernels (gfx950) for the fast evaluation of the lattice convolution sum
+//     f(x) = sum_n c_n phi(x - n),   phi = |det L| M_Xi(. + c0)
+// (Horacsek & Alim, Eq. conv_sum; the fast scheme of Sec. 4, Algorithm 1).
+//
+// One query per lane.  Per coset k (Sec. 4.1, Eq. coset_form):
+//   1. shift into the coset cell: i = floor((x - l_k)/D), u = x - l_k - D i - D/2
+//      (the map rho of Sec. 4.1 onto the region of evaluation [0, D)^s);
+//   2. fold u by a signed permutation T of the spline's symmetry group into the
+//      fundamental chamber (a sorting network on |u|; Sec. 4.3 symmetry
+//      analysis, used here instead of the sigma table of Sec. 4.2);
+//   3. select the sub-region from the few splitting planes left inside the
+//      chamber (predicated compares, Sec. 4.2);
+//   4. gather the sub-region's fixed stencil, renamed through T
+//      (pi(n) = T^{-1}(n - 1/2) + 1/2, the rigid renaming of Sec. 4.3);
+//   5. evaluate the sub-region's polynomial (generated straight-line code).
+// The coset contributions are summed (Algorithm 1, outer loop).
+//
+// The gathers read the coefficient arrays directly through the cache
+// hierarchy; the per-lane work is VALU FMAs.  No MFMA: the weights differ per
+// query, there is no shared dense operand.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsp {
+
+// ----------------------------------------------------------------------------
+// generated tables (one struct per spline)
+#include "generated/bcc_linear.inc"
+#include "generated/cc_zp.inc"
+#include "generated/bcc_quartic.inc"
+#include "generated/fcc_6dir.inc"
+#include "generated/d4s_8dir.inc"
+
+constexpr int kMaxCosets = 8;
+constexpr int kMaxDim = 4;
+
+// Coefficient volume: one array per coset, same dims, x fastest.
+struct Vol {
+  const void* base[kMaxCosets];
+  int dims[kMaxDim];
+  int stride[kMaxDim];  // elements
+};
+
+struct GradVol {
+  float* base[kMaxCosets];
+};
+
+// ----------------------------------------------------------------------------
+// coefficient storage types
+struct bf16_t { uint16_t v; };
+struct f16_t { _Float16 v; };
+
+template <class CT, class AT> __device__ __forceinline__ AT load_coef(const CT* p);
+template <> __device__ __forceinline__ float load_coef<float, float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ float load_coef<bf16_t, float>(const bf16_t* p) {
+  return __uint_as_float(static_cast<uint32_t>(p->v) << 16);
+}
+template <> __device__ __forceinline__ float load_coef<f16_t, float>(const f16_t* p) {
+  return static_cast<float>(p->v);
+}
+template <> __device__ __forceinline__ double load_coef<double, double>(const double* p) { return *p; }
+
+// ----------------------------------------------------------------------------
+// per-coset geometry of one query: cell index, folded point, folded strides
+template <class SP, class AT>
+struct Folded {
+  int i[SP::S];       // cell index (coset array index of the cell origin)
+  AT up[SP::S];       // folded offset from the cell centre, in the chamber
+  int ax[SP::S];      // folded axis r comes from original axis ax[r]
+  int sg[SP::S];      // and carries sign sg[r]: up[r] = sg[r] * u[ax[r]]
+  bool interior;      // the whole stencil lies inside the stored arrays
+};
+
+template <class AT> __device__ __forceinline__ AT afloor(AT v);
+template <> __device__ __forceinline__ float afloor<float>(float v) { return floorf(v); }
+template <> __device__ __forceinline__ double afloor<double>(double v) { return floor(v); }
+
+template <class SP, class AT>
+__device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, Folded<SP, AT>& F) {
+  constexpr int S = SP::S;
+  AT a[S];
+  bool interior = true;
+#pragma unroll
+  for (int d = 0; d < S; ++d) {
+    AT xp = x[d] - AT(SP::SHIFT[k][d]);
+    AT fl = afloor<AT>(xp * AT(1.0 / SP::D));
+    // keep the index arithmetic in range for huge or non-finite queries
+    fl = fl > AT(1 << 24) ? AT(1 << 24) : (fl < AT(-(1 << 24)) ? AT(-(1 << 24)) : fl);
+    int id = static_cast<int>(fl);
+    AT u = (xp - AT(SP::D) * fl) - AT(0.5 * SP::D);
+    F.i[d] = id;
+    interior = interior && (id + SP::OMIN >= 0) && (id + SP::OMAX < vol.dims[d]);
+    a[d] = u;
+    F.ax[d] = d;
+    F.sg[d] = (u >= AT(0)) ? 1 : -1;
+  }
+  F.interior = interior;
+  AT v[S];
+#pragma unroll
+  for (int d = 0; d < S; ++d) v[d] = a[d] < AT(0) ? -a[d] : a[d];
+  // sorting network, descending on |u|, carrying axis and sign
+  auto cswap = [&](int p, int q) {
+    bool sw = v[p] < v[q];
+    AT tv = sw ? v[q] : v[p]; AT uv = sw ? v[p] : v[q]; v[p] = tv; v[q] = uv;
+    int ta = sw ? F.ax[q] : F.ax[p]; int ua = sw ? F.ax[p] : F.ax[q]; F.ax[p] = ta; F.ax[q] = ua;
+    int ts = sw ? F.sg[q] : F.sg[p]; int us = sw ? F.sg[p] : F.sg[q]; F.sg[p] = ts; F.sg[q] = us;
+  };
+  if constexpr (S == 3) {
+    cswap(0, 1); cswap(1, 2); cswap(0, 1);
+  } else {
+    cswap(0, 1); cswap(2, 3); cswap(0, 2); cswap(1, 3); cswap(1, 2);
+  }
+  if constexpr (SP::FOLD_D) {
+    // even sign changes only: an odd number of negative components leaves the
+    // smallest folded coordinate negative
+    int neg = 0;
+#pragma unroll
+    for (int d = 0; d < S; ++d) neg += (F.sg[d] < 0);
+    if (neg & 1) { v[S - 1] = -v[S - 1]; F.sg[S - 1] = -F.sg[S - 1]; }
+  }
+#pragma unroll
+  for (int d = 0; d < S; ++d) F.up[d] = v[d];
+}
+
+// Gather through the fold: folded site J maps to original offset
+// o[ax[r]] = J[r] if sg[r] > 0 else 1 - J[r].
+template <class SP, class CT, class AT, bool CHECK>
+struct Gather {
+  const CT* origin;   // array element of folded site J = 0
+  const CT* safe;     // any valid element (used for masked loads)
+  int st[SP::S];      // folded signed strides
+  int jlo[SP::S], jhi[SP::S];  // CHECK: valid J range per folded axis
+
+  __device__ __forceinline__ void init(const Vol& vol, int k, const Folded<SP, AT>& F) {
+    const CT* base = static_cast<const CT*>(vol.base[k]);
+    safe = base;
+    long long off = 0;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) off += static_cast<long long>(F.i[d]) * vol.stride[d];
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const int a = F.ax[r];
+      const int s = vol.stride[a];
+      st[r] = F.sg[r] > 0 ? s : -s;
+      if (F.sg[r] < 0) off += s;
+      if constexpr (CHECK) {
+        const int ia = F.i[a], n = vol.dims[a];
+        // sg > 0: 0 <= ia + J < n ; sg < 0: 0 <= ia + 1 - J < n
+        jlo[r] = F.sg[r] > 0 ? -ia : ia + 2 - n;
+        jhi[r] = F.sg[r] > 0 ? n - 1 - ia : ia + 1;
+      }
+    }
+    origin = base + off;
+  }
+
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ AT c() const {
+    constexpr int J[4] = {J0, J1, J2, J3};
+    int off = 0;
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) off += J[r] * st[r];
+    if constexpr (CHECK) {
+      bool ok = true;
+#pragma unroll
+      for (int r = 0; r < SP::S; ++r) ok = ok && (J[r] >= jlo[r]) && (J[r] <= jhi[r]);
+      const CT* p = ok ? origin + off : safe;
+      AT v = load_coef<CT, AT>(p);
+      return ok ? v : AT(0);
+    } else {
+      return load_coef<CT, AT>(origin + off);
+    }
+  }
+};
+
+// Scatter-add of g * w_j into the gradient volume (adjoint, FP32 atomics).
+template <class SP, bool CHECK>
+struct Scatter {
+  float* origin;
+  int st[SP::S];
+  int jlo[SP::S], jhi[SP::S];
+  float g;
+
+  __device__ __forceinline__ void init(const Vol& vol, float* base, const Folded<SP, float>& F, float gq) {
+    long long off = 0;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) off += static_cast<long long>(F.i[d]) * vol.stride[d];
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const int a = F.ax[r];
+      const int s = vol.stride[a];
+      st[r] = F.sg[r] > 0 ? s : -s;
+      if (F.sg[r] < 0) off += s;
+      if constexpr (CHECK) {
+        const int ia = F.i[a], n = vol.dims[a];
+        jlo[r] = F.sg[r] > 0 ? -ia : ia + 2 - n;
+        jhi[r] = F.sg[r] > 0 ? n - 1 - ia : ia + 1;
+      }
+    }
+    origin = base + off;
+    g = gq;
+  }
+
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ void put(float w) {
+    constexpr int J[4] = {J0, J1, J2, J3};
+    int off = 0;
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) off += J[r] * st[r];
+    if constexpr (CHECK) {
+      bool ok = true;
+#pragma unroll
+      for (int r = 0; r < SP::S; ++r) ok = ok && (J[r] >= jlo[r]) && (J[r] <= jhi[r]);
+      if (ok) atomicAdd(origin + off, g * w);
+    } else {
+      atomicAdd(origin + off, g * w);
+    }
+  }
+};
+
+template <class SP, class AT>
+__device__ __forceinline__ void monomials(const AT* up, AT* mono) {
+  mono[0] = AT(1);
+#pragma unroll
+  for (int m = 1; m < SP::NMON; ++m) mono[m] = mono[SP::MPARENT[m]] * up[SP::MVAR[m]];
+}
+
+// psi and, optionally, its gradient in the folded frame from b and the monomials
+template <class SP, class AT, bool GRAD>
+__device__ __forceinline__ AT poly_eval(const AT* b, const AT* mono, AT* dpsi) {
+  AT psi = AT(0);
+#pragma unroll
+  for (int m = 0; m < SP::NMON; ++m) psi = fma(b[m], mono[m], psi);
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      AT acc = AT(0);
+#pragma unroll
+      for (int m = 0; m < SP::NMON; ++m) {
+        if (SP::MDER[m][r] >= 0) acc = fma(b[m] * AT(SP::MONO[m][r]), mono[SP::MDER[m][r]], acc);
+      }
+      dpsi[r] = acc;
+    }
+  }
+  return psi;
+}
+
+// one coset's contribution (value, and gradient in the original frame)
+template <class SP, class CT, class AT, bool GRAD>
+__device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* xq, AT& f, AT* gx) {
+  Folded<SP, AT> F;
+  fold_query<SP, AT>(xq, k, vol, F);
+  const int ob = SP::template orbit<AT>(F.up);
+  AT b[SP::NMON];
+  if (F.interior) {
+    Gather<SP, CT, AT, false> g;
+    g.init(vol, k, F);
+    SP::template b_any<AT>(ob, g, b);
+  } else {
+    Gather<SP, CT, AT, true> g;
+    g.init(vol, k, F);
+    SP::template b_any<AT>(ob, g, b);
+  }
+  AT mono[SP::NMON];
+  monomials<SP, AT>(F.up, mono);
+  AT dpsi[SP::S];
+  f += poly_eval<SP, AT, GRAD>(b, mono, dpsi);
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      // up[r] = sg[r] * u[ax[r]]  =>  d/du[ax[r]] = sg[r] * d/dup[r]
+      const AT v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : AT(0);
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// forward: f (and grad) at N queries, x as N x S float32 (row-major)
+template <class SP, class CT, class AT, bool GRAD>
+__global__ void __launch_bounds__(256) k_eval(Vol vol, const float* __restrict__ x, long long n,
+                                              AT* __restrict__ f, AT* __restrict__ grad) {
+  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  AT xq[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) xq[d] = static_cast<AT>(x[q * SP::S + d]);
+  AT acc = AT(0);
+  AT gx[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) gx[d] = AT(0);
+#pragma unroll
+  for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, AT, GRAD>(vol, k, xq, acc, gx);
+  f[q] = acc;
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = gx[d];
+  }
+}
+
+// forward with a mean-squared-error head: writes f, dL/df = 2 (f - y) / N and
+// accumulates L = sum (f - y)^2 / N into *loss (FP64 atomics, one per block)
+template <class SP, class CT>
+__global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restrict__ x, const float* __restrict__ y,
+                                                  long long n, float inv_n, float* __restrict__ f,
+                                                  float* __restrict__ dldf, double* __restrict__ loss) {
+  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  float r2 = 0.f;
+  if (q < n) {
+    float xq[SP::S];
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
+    float acc = 0.f;
+    float gx[SP::S];
+#pragma unroll
+    for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, float, false>(vol, k, xq, acc, gx);
+    const float r = acc - y[q];
+    f[q] = acc;
+    dldf[q] = 2.f * r * inv_n;
+    r2 = r * r;
+  }
+  // wave reduction, then one atomic per wave
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, static_cast<double>(r2) * static_cast<double>(inv_n));
+}
+
+// adjoint: grad_c[site] += g_q * w_site(x_q) (scatter-add), grad_x = g_q * grad f
+template <class SP, class CT, bool GRADX>
+__global__ void __launch_bounds__(256) k_adjoint(Vol vol, GradVol gvol, const float* __restrict__ x,
+                                                 const float* __restrict__ gout, long long n,
+                                                 float* __restrict__ grad_x) {
+  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  float xq[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
+  const float gq = gout[q];
+  float gx[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
+#pragma unroll
+  for (int k = 0; k < SP::M; ++k) {
+    Folded<SP, float> F;
+    fold_query<SP, float>(xq, k, vol, F);
+    const int ob = SP::template orbit<float>(F.up);
+    float mono[SP::NMON];
+    monomials<SP, float>(F.up, mono);
+    if (F.interior) {
+      Scatter<SP, false> sc;
+      sc.init(vol, gvol.base[k], F, gq);
+      SP::template w_any<float>(ob, sc, mono);
+    } else {
+      Scatter<SP, true> sc;
+      sc.init(vol, gvol.base[k], F, gq);
+      SP::template w_any<float>(ob, sc, mono);
+    }
+    if constexpr (GRADX) {
+      float b[SP::NMON];
+      if (F.interior) {
+        Gather<SP, CT, float, false> g;
+        g.init(vol, k, F);
+        SP::template b_any<float>(ob, g, b);
+      } else {
+        Gather<SP, CT, float, true> g;
+        g.init(vol, k, F);
+        SP::template b_any<float>(ob, g, b);
+      }
+      float dpsi[SP::S];
+      (void)poly_eval<SP, float, true>(b, mono, dpsi);
+#pragma unroll
+      for (int r = 0; r < SP::S; ++r) {
+        const float v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : 0.f;
+      }
+    }
+  }
+  if constexpr (GRADX) {
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) grad_x[q * SP::S + d] = gq * gx[d];
+  }
+}
+
+// Ray-marched samples (orthographic): sample (ray r, step j) is at
+//   p = c + A t,  t = ((2u+1)/W - 1, (2v+1)/H - 1, (2j+1)/S - 1)
+// with pixel (u, v) from the ray index in 8x8 tiles (one wave per tile).
+// Per ray: sum of f and of grad f over the steps (4 floats); optionally every
+// sample's f and grad f (4 floats each).
+struct RayParams {
+  float c[3];
+  float A[9];   // row-major 3x3
+  int W, H, steps;
+};
+
+__device__ __forceinline__ void ray_pixel(long long r, int W, int& u, int& v) {
+  const long long tile = r >> 6;
+  const int within = static_cast<int>(r & 63);
+  const int tiles_x = W >> 3;
+  u = static_cast<int>(tile % tiles_x) * 8 + (within & 7);
+  v = static_cast<int>(tile / tiles_x) * 8 + (within >> 3);
+}
+
+template <class SP, class CT>
+__global__ void __launch_bounds__(256) k_rays(Vol vol, RayParams rp, long long ray0, long long nrays,
+                                              float* __restrict__ out, float* __restrict__ samples) {
+  static_assert(SP::S == 3, "rays are 3-D");
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nrays) return;
+  const long long r = ray0 + t;
+  int pu, pv;
+  ray_pixel(r, rp.W, pu, pv);
+  // exact in float32: (2u+1)/W - 1 for power-of-two W
+  const float tu = __fsub_rn(__fmul_rn(static_cast<float>(2 * pu + 1), 1.0f / rp.W), 1.0f);
+  const float tv = __fsub_rn(__fmul_rn(static_cast<float>(2 * pv + 1), 1.0f / rp.H), 1.0f);
+  float base[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    base[a] = __fadd_rn(__fadd_rn(rp.c[a], __fmul_rn(rp.A[3 * a + 0], tu)), __fmul_rn(rp.A[3 * a + 1], tv));
+  float sf = 0.f, sg0 = 0.f, sg1 = 0.f, sg2 = 0.f;
+  const float invs = 1.0f / rp.steps;
+  for (int j = 0; j < rp.steps; ++j) {
+    const float tj = __fsub_rn(__fmul_rn(static_cast<float>(2 * j + 1), invs), 1.0f);
+    float xq[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xq[a] = __fadd_rn(base[a], __fmul_rn(rp.A[3 * a + 2], tj));
+    float f = 0.f;
+    float gx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, float, true>(vol, k, xq, f, gx);
+    sf += f; sg0 += gx[0]; sg1 += gx[1]; sg2 += gx[2];
+    if (samples) {
+      float* o = samples + (t * rp.steps + j) * 4;
+      o[0] = f; o[1] = gx[0]; o[2] = gx[1]; o[3] = gx[2];
+    }
+  }
+  out[t * 4 + 0] = sf; out[t * 4 + 1] = sg0; out[t * 4 + 2] = sg1; out[t * 4 + 3] = sg2;
+}
+
+}  // namespace lsp

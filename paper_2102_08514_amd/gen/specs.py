@@ -1,0 +1,30 @@
+"""The splines the library ships tables for (lattice matrix, direction matrix)."""
+
+I3 = [[1, 0, 0], [0, 1, 0], [0, 0, 1]]
+BCC_DIAG = [[-1, 1, 1, -1], [1, -1, 1, -1], [1, 1, -1, -1]]
+HAD4 = [[1, 1, 1, 1], [1, 1, -1, -1], [1, -1, 1, -1], [1, -1, -1, 1]]
+
+
+def _hcat(*ms):
+    return [sum((list(m[r]) for m in ms), []) for r in range(len(ms[0]))]
+
+
+def _scale(m, k):
+    return [[k * v for v in row] for row in m]
+
+
+L_CC = I3
+L_BCC = [[-1, 1, 1], [1, -1, 1], [1, 1, -1]]
+L_FCC = [[0, 1, 1], [1, 0, 1], [1, 1, 0]]
+L_D4S = [[2, 0, 0, 1], [0, 2, 0, 1], [0, 0, 2, 1], [0, 0, 0, 1]]
+I4 = [[int(a == b) for b in range(4)] for a in range(4)]
+HAD4_COLS = [list(r) for r in zip(*HAD4)]  # columns of the Hadamard matrix as rows
+
+SPECS = {
+    # name: (struct name, L, Xi)
+    "bcc_linear": ("SplineBccLinear", L_BCC, BCC_DIAG),
+    "cc_zp": ("SplineCcZp", L_CC, _hcat(I3, BCC_DIAG)),
+    "bcc_quartic": ("SplineBccQuartic", L_BCC, _hcat(_scale(I3, 2), BCC_DIAG)),
+    "fcc_6dir": ("SplineFcc6", L_FCC, [[1, -1, 1, 1, 0, 0], [1, 1, 0, 0, 1, -1], [0, 0, 1, -1, 1, 1]]),
+    "d4s_8dir": ("SplineD4s8", L_D4S, _hcat(_scale(I4, 2), [list(r) for r in zip(*HAD4_COLS)])),
+}

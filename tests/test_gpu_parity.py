@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Sizes span several 256-query blocks with a ragged tail; queries include
+interior points, points on lattice sites and mesh planes, and points whose
+support leaves the stored arrays (zero extension).  Tolerances (normwise,
+relative to max |c|): FP32 1e-5, FP64 accumulation 1e-11, BF16 storage
+2e-3 against the unrounded coefficients and 1e-5 against the rounded ones.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ConvolutionSumOracle
+from workloads import configs as W
+from workloads import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 10, 10), "c5": (7, 7, 7, 7)}
+NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def small_case(name, n=None, seed=0):
+    cfg = W.get(name)
+    dims = SMALL[name]
+    rng = np.random.default_rng(1000 + seed)
+    coeffs = [rng.uniform(-1, 1, tuple(reversed(dims))) for _ in range(cfg.M)]
+    n = NQ[name] if n is None else n
+    ext = cfg.D * (dims[0] - 1) + 1
+    # mostly interior, some straddling the border (zero extension), a few outside
+    X = rng.uniform(-2.0, ext + 1.0, (n, cfg.s))
+    X[: n // 2] = rng.uniform(cfg.D * 2, ext - cfg.D * 2 - 1, (n // 2, cfg.s))
+    # lattice sites, half-integers and cell centres exactly
+    special = rng.integers(3, ext - 4, (48, cfg.s)).astype(float)
+    special[16:32] += 0.5
+    special[32:40] += rng.integers(0, 2, (8, cfg.s)) * 0.25
+    X[-48:] = special
+    return cfg, coeffs, X.astype(np.float32)
+
+
+def to_dev(arrs, dtype):
+    torch = _torch()
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda() for a in arrs]
+
+
+def normwise(a, b, coeffs):
+    scale = max(float(np.max(np.abs(c))) for c in coeffs)
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)))) / scale
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+def test_forward_fp32(lsp, name):
+    torch = _torch()
+    cfg, coeffs, X = small_case(name)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval(coeffs, X.astype(np.float64))
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    c32 = [c.astype(np.float32).astype(np.float64) for c in coeffs]
+    want32 = o.eval(c32, X.astype(np.float64))
+    f = sp.eval(vol, torch.from_numpy(X).cuda()).cpu().numpy()
+    print(name, "fp32 normwise err", normwise(f, want32, coeffs), flush=True)
+    assert normwise(f, want32, coeffs) <= 1e-5
+    assert normwise(f, want, coeffs) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+def test_forward_fp64_check(lsp, name):
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, seed=1)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval(coeffs, X.astype(np.float64))
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float64))
+    f = sp.eval(vol, torch.from_numpy(X).cuda())
+    assert f.dtype == torch.float64
+    err = normwise(f.cpu().numpy(), want, coeffs)
+    print(name, "fp64 normwise err", err, flush=True)
+    assert err <= 1e-11
+
+
+@pytest.mark.parametrize("name,dt", [("c2", "bf16"), ("c3", "bf16"), ("c5", "bf16"), ("c3", "f16")])
+def test_forward_low_precision_storage(lsp, name, dt):
+    torch = _torch()
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dt]
+    cfg, coeffs, X = small_case(name, seed=2)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    dev = to_dev(coeffs, tdt)              # round-to-nearest-even conversion
+    rounded = [d.float().cpu().numpy().astype(np.float64) for d in dev]
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(dev)
+    f = sp.eval(vol, torch.from_numpy(X).cuda()).cpu().numpy()
+    assert normwise(f, o.eval(coeffs, X.astype(np.float64)), coeffs) <= 2e-3
+    assert normwise(f, o.eval(rounded, X.astype(np.float64)), coeffs) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c5"])
+def test_gradient(lsp, name):
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, seed=3)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    _, gw = o.eval(coeffs, X.astype(np.float64), want_grad=True)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    f, g = sp.eval(vol, torch.from_numpy(X).cuda(), grad=True)
+    err = normwise(g.cpu().numpy(), gw, coeffs)
+    print(name, "grad normwise err", err, flush=True)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
+def test_adjoint(lsp, name):
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, seed=4)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    rng = np.random.default_rng(5)
+    g = rng.normal(size=len(X)).astype(np.float32)
+    want = o.adjoint(X.astype(np.float64), g.astype(np.float64), SMALL[name])
+    bound = max(float(np.max(a)) for a in o.adjoint(X.astype(np.float64), np.abs(g).astype(np.float64),
+                                                      SMALL[name]))
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    gc, gx = sp.adjoint(vol, torch.from_numpy(X).cuda(), torch.from_numpy(g).cuda(), grad_x=True)
+    for a, b in zip(gc, want):
+        assert float(np.max(np.abs(a.cpu().numpy() - b))) <= 1e-5 * bound
+    if name != "c1":   # c1 is only C0: its gradient is two-valued on the mesh planes
+        _, gw = o.eval(coeffs, X.astype(np.float64), want_grad=True)
+        assert normwise(gx.cpu().numpy(), g[:, None] * gw, coeffs) <= 1e-4 * max(1.0, float(np.max(np.abs(g))))
+
+
+@pytest.mark.parametrize("name", ["c4", "c5"])
+def test_mse_head(lsp, name):
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, seed=6)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    y = I.targets(cfg, X)
+    c32 = [c.astype(np.float32).astype(np.float64) for c in coeffs]
+    want = o.eval(c32, X.astype(np.float64))
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    f, dldf, loss = sp.eval_mse(vol, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda())
+    n = len(X)
+    r = want - y
+    assert normwise(f.cpu().numpy(), want, coeffs) <= 1e-5
+    np.testing.assert_allclose(dldf.cpu().numpy(), 2 * r / n, atol=2e-5 / n * 4)
+    assert abs(float(loss.item()) - float(np.mean(r * r))) <= 1e-5 * max(1.0, float(np.mean(r * r)))
+
+
+def test_autograd_backward_matches_adjoint(lsp):
+    torch = _torch()
+    cfg, coeffs, X = small_case("c4", seed=7)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    cs = [t.requires_grad_(True) for t in to_dev(coeffs, torch.float32)]
+    x = torch.from_numpy(X).cuda().requires_grad_(True)
+    f = lsp.lattice_spline(sp, x, cs)
+    y = torch.from_numpy(I.targets(cfg, X)).cuda()
+    loss = ((f - y) ** 2).mean()
+    loss.backward()
+    g = (2.0 * (f.detach() - y) / len(X)).double().cpu().numpy()
+    want = o.adjoint(X.astype(np.float64), g, SMALL["c4"])
+    bound = max(float(np.max(a)) for a in o.adjoint(X.astype(np.float64), np.abs(g), SMALL["c4"]))
+    for c, w in zip(cs, want):
+        assert float(np.max(np.abs(c.grad.cpu().numpy() - w))) <= 1e-5 * bound + 1e-9
+
+
+def _tile_pixels(rays, W):
+    r = np.asarray(rays)
+    tile, within = r >> 6, r & 63
+    u = (tile % (W // 8)) * 8 + (within & 7)
+    v = (tile // (W // 8)) * 8 + (within >> 3)
+    return u + W * v
+
+
+def test_rays_against_oracle(lsp):
+    torch = _torch()
+    cfg = W.get("c3")
+    dims = (16, 16, 16)
+    rng = np.random.default_rng(8)
+    coeffs = [rng.uniform(-1, 1, tuple(reversed(dims))) for _ in range(2)]
+    centre = np.full(3, 15.5)
+    a = 11.0 / np.sqrt(3.0)
+    cz, sz = math.cos(math.radians(30.0)), math.sin(math.radians(30.0))
+    cx, sx = math.cos(math.radians(20.0)), math.sin(math.radians(20.0))
+    R = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]]) @ np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    A = (R * a).astype(np.float32)
+    Wd, H, S = 16, 8, 37
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    ray0, nrays = 5, 100
+    out, smp = sp.rays(vol, centre.astype(np.float32), A, Wd, H, S, ray0=ray0, nrays=nrays, samples=True)
+    rays = np.arange(ray0, ray0 + nrays)
+    pix = _tile_pixels(rays, Wd)
+    # the same float32 sample positions, computed independently on the CPU
+    c32, A32 = centre.astype(np.float32), A
+    u = (pix % Wd).astype(np.float32)
+    v = (pix // Wd).astype(np.float32)
+    j = np.arange(S, dtype=np.float32)
+    tu = (np.float32(2) * (u + np.float32(0.5))) / np.float32(Wd) - np.float32(1)
+    tv = (np.float32(2) * (v + np.float32(0.5))) / np.float32(H) - np.float32(1)
+    tj = (np.float32(2) * (j + np.float32(0.5))) / np.float32(S) - np.float32(1)
+    P = np.empty((nrays, S, 3), dtype=np.float32)
+    for ax in range(3):
+        base = (c32[ax] + A32[ax, 0] * tu) + A32[ax, 1] * tv
+        P[:, :, ax] = base[:, None] + A32[ax, 2] * tj[None, :]
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    fw, gw = o.eval([c.astype(np.float32).astype(np.float64) for c in coeffs],
+                    P.reshape(-1, 3).astype(np.float64), want_grad=True)
+    smp = smp.cpu().numpy().reshape(-1, 4)
+    assert normwise(smp[:, 0], fw, coeffs) <= 1e-5
+    assert normwise(smp[:, 1:], gw, coeffs) <= 1e-4
+    out = out.cpu().numpy()
+    np.testing.assert_allclose(out[:, 0], fw.reshape(nrays, S).sum(1), atol=S * 1e-5)
+    np.testing.assert_allclose(out[:, 1:], gw.reshape(nrays, S, 3).sum(1), atol=S * 1e-4)
+
+
+def test_edge_cases(lsp):
+    torch = _torch()
+    cfg, coeffs, X = small_case("c2", n=300, seed=9)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    # empty batch
+    f = sp.eval(vol, torch.empty(0, 3, device="cuda"))
+    assert f.numel() == 0
+    # non-finite queries give NaN and do not fault
+    bad = torch.tensor([[float("nan"), 3.0, 3.0], [float("inf"), 3.0, 3.0], [-float("inf"), 1e30, 3.0],
+                        [5.0, 5.0, 5.0]], device="cuda")
+    fb = sp.eval(vol, bad).cpu().numpy()
+    assert np.isnan(fb[0]) and not np.isnan(fb[3])
+    # far outside the volume: zero
+    far = torch.tensor([[-100.0, -100.0, -100.0], [1e6, 1e6, 1e6]], device="cuda")
+    assert np.all(sp.eval(vol, far).cpu().numpy() == 0)
+    # constant data reproduces the constant in the interior (partition of unity)
+    ones = [torch.ones_like(c) for c in vol.coeffs]
+    v1 = sp.bind(ones)
+    Xi = torch.from_numpy(np.random.default_rng(1).uniform(4, 15, (777, 3)).astype(np.float32)).cuda()
+    assert float((sp.eval(v1, Xi) - 1).abs().max()) < 2e-6
+
+
+def test_full_size_sampled_c2(lsp):
+    """The benchmark's workload (256^3 volume, 2^24 queries, same launch),
+    checked on a sample of outputs against the oracle."""
+    torch = _torch()
+    cfg = W.get("c2")
+    coeffs = I.coefficients(cfg)
+    X = I.queries(cfg)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    f = sp.eval(vol, torch.from_numpy(X).cuda()).cpu().numpy()
+    idx = np.random.default_rng(10).choice(len(X), 2048, replace=False)
+    idx = np.concatenate([idx, [0, len(X) - 1]])
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
+    assert normwise(f[idx], want, coeffs) <= 1e-5
+    assert np.all(np.isfinite(f))
