@@ -71,22 +71,32 @@ def cpu_baseline(name, coeffs, X, target_s=8.0):
 
 
 # ------------------------------------------------------------------ GPU legs
-def time_launches(fn, steps, warmup, torch):
+def time_launches(fn, steps, warmup, torch, split=False):
     """Run fn() `warmup` times, then time `steps` calls: wall time between two
-    synchronisations, plus the per-launch duration from HIP events recorded on
-    the stream the library launches on (torch's current stream)."""
+    synchronisations, plus durations from HIP events recorded on the stream the
+    library launches on (torch's current stream).  With split=True, fn records
+    a middle event between scheduling and evaluation; returns the evaluation
+    part's mean/median and the scheduling part's mean."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    ev = [(E(), E(), E()) for _ in range(steps)]
     t0 = time.perf_counter()
-    for a, b in ev:
+    for a, m, b in ev:
         a.record()
-        fn()
+        if split:
+            fn(m)
+        else:
+            fn()
         b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per = [a.elapsed_time(b) / 1e3 for a, b in ev]
+    if split:
+        per = [m.elapsed_time(b) / 1e3 for a, m, b in ev]
+        pre = [a.elapsed_time(m) / 1e3 for a, m, b in ev]
+        return wall, float(np.mean(per)), float(np.median(per)), float(np.mean(pre))
+    per = [a.elapsed_time(b) / 1e3 for a, m, b in ev]
     return wall, float(np.mean(per)), float(np.median(per))
 
 
@@ -98,6 +108,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--order", default="sorted", choices=["sorted", "given"],
+                    help="evaluate in the library's scheduled order (timed) or in the given order")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method has no cross-GPU step in this build "
@@ -124,15 +136,22 @@ def main():
     s = cfg.s
     out_b = 8 if tdt == torch.float64 else 4
 
+    strm = torch.cuda.current_stream().cuda_stream
+    from paper_2102_08514_amd import _lib as Lb
+    given = None
+    sched_ms = None
     if args.config == "c3":
         W_, H_ = cfg.extra["rays"]
         S_ = cfg.extra["steps"]
         c, A = I.ray_params(cfg)
         n = W_ * H_ * S_
         out = torch.empty(W_ * H_, 4, device="cuda")
+        cf, Af = c.astype(np.float32), A.astype(np.float32)
 
-        def step():
-            sp.rays(vol, c.astype(np.float32), A.astype(np.float32), W_, H_, S_)
+        def step(ev=None):
+            if ev is not None:
+                ev.record()
+            sp.rays(vol, cf, Af, W_, H_, S_)
         bytes_per = Lq * bytes_c + 16.0 / S_                     # coefficients + per-ray output
         X = None
     else:
@@ -140,33 +159,58 @@ def main():
         n = len(X)
         x = torch.from_numpy(X).cuda()
         f = torch.empty(n, device="cuda", dtype=vol.out_dtype)
+        ws_bytes = Lb.lsp_schedule_size(sp.plan, vol.handle, n)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        use_sched = args.order == "sorted"
         if cfg.passes == "mse":
             y = torch.from_numpy(I.targets(cfg, X)).cuda()
             loss = torch.zeros(1, device="cuda", dtype=torch.float64)
             dldf = torch.empty(n, device="cuda")
             gradc = [torch.zeros(c.shape, device="cuda") for c in dev]
             gx = torch.empty(n, s, device="cuda")
-            from paper_2102_08514_amd import _lib as Lb
-            strm = torch.cuda.current_stream().cuda_stream
 
-            def step():
+            def step(ev=None, sched=use_sched):
+                if sched:
+                    Lb.lsp_schedule(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes, strm)
+                if ev is not None:
+                    ev.record()
                 loss.zero_()
-                Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(), dldf.data_ptr(),
-                                loss.data_ptr(), strm)
                 for g in gradc:
                     g.zero_()
-                Lb.lsp_eval_adjoint(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
-                                    [g.data_ptr() for g in gradc], gx.data_ptr(), strm)
+                if sched:
+                    Lb.lsp_eval_mse_scheduled(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, ws.data_ptr(),
+                                              ws_bytes, f.data_ptr(), dldf.data_ptr(), loss.data_ptr(), strm)
+                    Lb.lsp_eval_adjoint_scheduled(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
+                                                  ws.data_ptr(), ws_bytes, [g.data_ptr() for g in gradc],
+                                                  gx.data_ptr(), strm)
+                else:
+                    Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(),
+                                    dldf.data_ptr(), loss.data_ptr(), strm)
+                    Lb.lsp_eval_adjoint(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
+                                        [g.data_ptr() for g in gradc], gx.data_ptr(), strm)
             # fwd: x + y + coefficients + f + dL/df; bwd: x + dL/df + coefficients (regather) +
             # scatter (4 B each) + grad_x
             bytes_per = (4 * s + 4 + Lq * bytes_c + 8) + (4 * s + 4 + Lq * bytes_c + Lq * 4 + 4 * s)
         else:
-            def step():
-                sp.eval(vol, x, out=f)
+            def step(ev=None, sched=use_sched):
+                if sched:
+                    Lb.lsp_schedule(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes, strm)
+                if ev is not None:
+                    ev.record()
+                if sched:
+                    Lb.lsp_eval_scheduled(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes,
+                                          f.data_ptr(), None, strm)
+                else:
+                    Lb.lsp_eval(sp.plan, vol.handle, x.data_ptr(), n, f.data_ptr(), None, strm)
             bytes_per = 4 * s + Lq * bytes_c + out_b
+        if use_sched:
+            # context: the same step on the queries in their given order
+            gw, gm, _ = time_launches(lambda ev=None: step(ev, sched=False), max(3, args.steps // 4), 1, torch)
+            given = {"ms_per_step": round(gw / max(3, args.steps // 4) * 1e3, 4),
+                     "value": round(n / (gw / max(3, args.steps // 4)) / 1e9, 4)}
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up")
-    wall, mean_launch, med_launch = time_launches(step, args.steps, args.warmup, torch)
+    wall, mean_launch, med_launch, sched_mean = time_launches(step, args.steps, args.warmup, torch, split=True)
     ms_per_step = wall / args.steps * 1e3
     value = n / (wall / args.steps) / 1e9
     achieved = bytes_per * n / mean_launch / 1e9
@@ -186,12 +230,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "spline": info["name"],
                    "n_samples": n, "lookups_per_sample": Lq, "volume_dims": list(cfg.dims),
-                   "n_cosets": cfg.M, "passes": cfg.passes},
+                   "n_cosets": cfg.M, "passes": cfg.passes,
+                   "order": "rays" if X is None else args.order},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_sample": round(bytes_per, 3),
-                     "kernel_ms_mean": round(mean_launch * 1e3, 4), "kernel_ms_median": round(med_launch * 1e3, 4)},
+                     "eval_ms_mean": round(mean_launch * 1e3, 4), "eval_ms_median": round(med_launch * 1e3, 4)},
     }
+    if sched_mean is not None and X is not None and args.order == "sorted":
+        rec["schedule_ms_mean"] = round(sched_mean * 1e3, 4)
+    if given is not None:
+        rec["given_order"] = given
     if not args.no_cpu and X is not None:
         log("[bench] CPU oracle leg")
         cb, idx, want = cpu_baseline(args.config, coeffs if tdt != torch.float32 else

@@ -131,6 +131,37 @@ lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const fl
 lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
                          int32_t steps, int64_t ray0, int64_t nrays, float* out, float* samples, void* stream);
 
+/* Query schedule (evaluation order).  Random queries gather from random
+ * places of the volume; ordering the work items so that neighbouring lanes
+ * read neighbouring coefficients makes the stencil gathers hit the caches
+ * (the paper notes that combining the reads of a coset exploits data
+ * locality, Sec. 4).  lsp_schedule computes that order with a counting sort
+ * on the GPU: key = Morton index of the query's brick of cells (8^3 cells in
+ * 3-D, 4^4 in 4-D, coarser for volumes above 2^20 keys) and, for splines
+ * with several sub-regions after the fold, the sub-region -- then one item is
+ * one (query, coset) pair, so a wave evaluates one polynomial set instead of
+ * all of them (the branch predication of Sec. 4.3 is avoided).
+ *
+ * lsp_schedule_size: device workspace bytes for n queries (depends on the
+ * plan, the volume dims and n).  lsp_schedule: fills that caller-owned,
+ * 256-byte aligned workspace from the queries x (no allocation).  The
+ * *_scheduled calls then evaluate the same x (same n) in that order; results
+ * land at each query's own index, exactly as the unscheduled calls.
+ * Errors: LSP_ERR_NULL, LSP_ERR_INVALID (workspace too small or misaligned,
+ * n * cosets >= 2^32).  With several sub-regions, f and grad_x are
+ * accumulated with float atomics over the cosets (summation order not fixed). */
+lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes);
+lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace, size_t ws_bytes,
+                        void* stream);
+lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
+                              size_t ws_bytes, void* f, void* grad_x, void* stream);
+lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n,
+                                  const void* workspace, size_t ws_bytes, float* f, float* dloss_df, double* loss,
+                                  void* stream);
+lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
+                                      const void* workspace, size_t ws_bytes, float* const* grad_c, float* grad_x,
+                                      void* stream);
+
 const char* lsp_status_string(lsp_status status);
 
 #ifdef __cplusplus

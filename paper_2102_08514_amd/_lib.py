@@ -16,6 +16,8 @@ LSP_F32, LSP_BF16, LSP_F16, LSP_F64 = 0, 1, 2, 3
 EXPORTS = (
     "lsp_plan_create", "lsp_plan_info", "lsp_plan_destroy", "lsp_vol_bind", "lsp_vol_release",
     "lsp_eval", "lsp_eval_mse", "lsp_eval_adjoint", "lsp_eval_rays", "lsp_status_string",
+    "lsp_schedule_size", "lsp_schedule", "lsp_eval_scheduled", "lsp_eval_mse_scheduled",
+    "lsp_eval_adjoint_scheduled",
 )
 
 
@@ -57,6 +59,12 @@ def lib():
         L.lsp_eval_adjoint.argtypes = [vp, vp, vp, vp, i64, P(vp), vp, vp]
         L.lsp_eval_rays.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), i32, i32, i32, i64, i64, vp, vp,
                                     vp]
+        sz = ctypes.c_size_t
+        L.lsp_schedule_size.argtypes = [vp, vp, i64, P(sz)]
+        L.lsp_schedule.argtypes = [vp, vp, vp, i64, vp, sz, vp]
+        L.lsp_eval_scheduled.argtypes = [vp, vp, vp, i64, vp, sz, vp, vp, vp]
+        L.lsp_eval_mse_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp, vp, vp, vp]
+        L.lsp_eval_adjoint_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, P(vp), vp, vp]
         L.lsp_status_string.argtypes = [i32]
         L.lsp_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -139,3 +147,29 @@ def lsp_eval_rays(plan, vol, c, A, W, H, steps, ray0, nrays, out_ptr, samples_pt
     AA = (ctypes.c_float * 9)(*[float(v) for v in A])
     check(lib().lsp_eval_rays(plan, vol, cc, AA, int(W), int(H), int(steps), int(ray0), int(nrays), out_ptr,
                               samples_ptr, stream), "lsp_eval_rays")
+
+
+def lsp_schedule_size(plan, vol, n):
+    out = ctypes.c_size_t()
+    check(lib().lsp_schedule_size(plan, vol, int(n), ctypes.byref(out)), "lsp_schedule_size")
+    return out.value
+
+
+def lsp_schedule(plan, vol, x_ptr, n, ws_ptr, ws_bytes, stream):
+    check(lib().lsp_schedule(plan, vol, x_ptr, int(n), ws_ptr, int(ws_bytes), stream), "lsp_schedule")
+
+
+def lsp_eval_scheduled(plan, vol, x_ptr, n, ws_ptr, ws_bytes, f_ptr, grad_ptr, stream):
+    check(lib().lsp_eval_scheduled(plan, vol, x_ptr, int(n), ws_ptr, int(ws_bytes), f_ptr, grad_ptr, stream),
+          "lsp_eval_scheduled")
+
+
+def lsp_eval_mse_scheduled(plan, vol, x_ptr, y_ptr, n, ws_ptr, ws_bytes, f_ptr, dldf_ptr, loss_ptr, stream):
+    check(lib().lsp_eval_mse_scheduled(plan, vol, x_ptr, y_ptr, int(n), ws_ptr, int(ws_bytes), f_ptr, dldf_ptr,
+                                       loss_ptr, stream), "lsp_eval_mse_scheduled")
+
+
+def lsp_eval_adjoint_scheduled(plan, vol, x_ptr, g_ptr, n, ws_ptr, ws_bytes, grad_c_ptrs, grad_x_ptr, stream):
+    arr = (ctypes.c_void_p * len(grad_c_ptrs))(*[int(p) for p in grad_c_ptrs])
+    check(lib().lsp_eval_adjoint_scheduled(plan, vol, x_ptr, g_ptr, int(n), ws_ptr, int(ws_bytes), arr, grad_x_ptr,
+                                           stream), "lsp_eval_adjoint_scheduled")

@@ -58,6 +58,19 @@ class Volume:
             self.handle = None
 
 
+class Schedule:
+    """Evaluation order for one batch of queries (device workspace)."""
+
+    def __init__(self, spline, vol, x):
+        _require_device(x)
+        self.n = x.shape[0]
+        self.bytes = L.lsp_schedule_size(spline.plan, vol.handle, self.n)
+        # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks
+        self.ws = torch.empty(max(self.bytes, 1), dtype=torch.uint8, device=x.device)
+        self.x = x
+        L.lsp_schedule(spline.plan, vol.handle, x.data_ptr(), self.n, self.ws.data_ptr(), self.bytes, _stream())
+
+
 class LatticeSpline:
     """A plan for lattice L and direction matrix Xi (generated tables must exist)."""
 
@@ -78,8 +91,12 @@ class LatticeSpline:
     def bind(self, coeffs):
         return Volume(self, coeffs)
 
+    def schedule(self, vol, x):
+        """Sort the queries x into cache-friendly evaluation order (see lsp_schedule)."""
+        return Schedule(self, vol, x)
+
     # ------------------------------------------------------------- forward
-    def eval(self, vol, x, grad=False, out=None, grad_out=None):
+    def eval(self, vol, x, grad=False, out=None, grad_out=None, schedule=None):
         _require_device(x)
         if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != self.s:
             raise ValueError("x must be an N x s float32 tensor")
@@ -88,28 +105,49 @@ class LatticeSpline:
         g = None
         if grad:
             g = grad_out if grad_out is not None else torch.empty(n, self.s, device=x.device, dtype=vol.out_dtype)
-        L.lsp_eval(self.plan, vol.handle, x.data_ptr(), n, f.data_ptr(), _ptr(g), _stream())
+        if schedule is None:
+            L.lsp_eval(self.plan, vol.handle, x.data_ptr(), n, f.data_ptr(), _ptr(g), _stream())
+        else:
+            self._check_sched(schedule, x)
+            L.lsp_eval_scheduled(self.plan, vol.handle, x.data_ptr(), n, schedule.ws.data_ptr(), schedule.bytes,
+                                 f.data_ptr(), _ptr(g), _stream())
         return (f, g) if grad else f
 
-    def eval_mse(self, vol, x, y):
+    @staticmethod
+    def _check_sched(schedule, x):
+        if schedule.n != x.shape[0] or schedule.x.data_ptr() != x.data_ptr():
+            raise ValueError("the schedule was built for other queries")
+
+    def eval_mse(self, vol, x, y, schedule=None):
         _require_device(x, y)
         n = x.shape[0]
         f = torch.empty(n, device=x.device, dtype=torch.float32)
         dldf = torch.empty(n, device=x.device, dtype=torch.float32)
         loss = torch.zeros(1, device=x.device, dtype=torch.float64)
-        L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(), dldf.data_ptr(),
-                       loss.data_ptr(), _stream())
+        if schedule is None:
+            L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(), dldf.data_ptr(),
+                           loss.data_ptr(), _stream())
+        else:
+            self._check_sched(schedule, x)
+            L.lsp_eval_mse_scheduled(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, schedule.ws.data_ptr(),
+                                     schedule.bytes, f.data_ptr(), dldf.data_ptr(), loss.data_ptr(), _stream())
         return f, dldf, loss
 
-    def adjoint(self, vol, x, g, grad_x=False, grad_c=None):
+    def adjoint(self, vol, x, g, grad_x=False, grad_c=None, schedule=None):
         """grad_c (zero-initialised here unless given) += A^T g; grad_x = g * grad f."""
         _require_device(x, g)
         n = x.shape[0]
         if grad_c is None:
             grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
         gx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
-        L.lsp_eval_adjoint(self.plan, vol.handle, x.data_ptr(), g.data_ptr(), n, [t.data_ptr() for t in grad_c],
-                           _ptr(gx), _stream())
+        if schedule is None:
+            L.lsp_eval_adjoint(self.plan, vol.handle, x.data_ptr(), g.data_ptr(), n, [t.data_ptr() for t in grad_c],
+                               _ptr(gx), _stream())
+        else:
+            self._check_sched(schedule, x)
+            L.lsp_eval_adjoint_scheduled(self.plan, vol.handle, x.data_ptr(), g.data_ptr(), n,
+                                         schedule.ws.data_ptr(), schedule.bytes, [t.data_ptr() for t in grad_c],
+                                         _ptr(gx), _stream())
         return grad_c, gx
 
     def rays(self, vol, centre, A, W, H, steps, ray0=0, nrays=None, samples=False):

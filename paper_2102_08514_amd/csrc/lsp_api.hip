@@ -126,76 +126,221 @@ std::vector<int> canon_dir(std::vector<int> v) {
   return std::max(v, neg);
 }
 
-template <class SP, class CT, class AT>
-lsp_status launch_eval(const lsp_vol_s* v, const float* x, int64_t n, void* f, void* grad, hipStream_t st) {
-  const int block = 256;
-  const long long grid = (n + block - 1) / block;
-  if (grad)
-    hipLaunchKernelGGL((k_eval<SP, CT, AT, true>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, x,
-                       static_cast<long long>(n), static_cast<AT*>(f), static_cast<AT*>(grad));
+// ---------------------------------------------------------------------------
+// schedule geometry and workspace layout (all uint32):
+//   count[nkeys] offset[nkeys] partial[1024] key[items] rank[items] perm[items]
+struct Sched {
+  bool split;
+  long long items;
+  SchedGeom g;
+  unsigned nkeys;
+  size_t off_count, off_offset, off_partial, off_key, off_rank, off_perm, bytes;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <class SP>
+Sched make_sched(const lsp_vol_s* v, int64_t n) {
+  Sched sc{};
+  sc.split = SP::K > 1;
+  sc.items = sc.split ? n * SP::M : n;
+  int bshift = SP::S == 3 ? 3 : 2;
+  for (;;) {
+    int maxnb = 1;
+    for (int d = 0; d < SP::S; ++d) {
+      sc.g.nb[d] = ((v->vol.dims[d] + (1 << bshift) - 1) >> bshift) + 1;
+      maxnb = std::max(maxnb, sc.g.nb[d]);
+    }
+    int nbits = 0;
+    while ((1 << nbits) < maxnb) ++nbits;
+    const unsigned long long nkeys = static_cast<unsigned long long>(sc.split ? SP::K : 1) << (nbits * SP::S);
+    if (nkeys <= (1ull << 20)) {
+      sc.g.bshift = bshift;
+      sc.g.nbits = nbits;
+      sc.nkeys = static_cast<unsigned>(nkeys);
+      break;
+    }
+    ++bshift;
+  }
+  size_t o = 0;
+  sc.off_count = o; o = align256(o + 4ull * sc.nkeys);
+  sc.off_offset = o; o = align256(o + 4ull * sc.nkeys);
+  sc.off_partial = o; o = align256(o + 4ull * 1024);
+  sc.off_key = o; o = align256(o + 4ull * sc.items);
+  sc.off_rank = o; o = align256(o + 4ull * sc.items);
+  sc.off_perm = o; o = align256(o + 4ull * sc.items);
+  sc.bytes = o;
+  return sc;
+}
+
+unsigned grid_of(long long n, int block = 256) { return static_cast<unsigned>((n + block - 1) / block); }
+unsigned fill_grid(long long n) { return static_cast<unsigned>(std::min<long long>((n + 255) / 256, 4096)); }
+
+template <class SP>
+lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
+  const Sched sc = make_sched<SP>(v, n);
+  char* base = static_cast<char*>(ws);
+  unsigned* count = reinterpret_cast<unsigned*>(base + sc.off_count);
+  unsigned* offset = reinterpret_cast<unsigned*>(base + sc.off_offset);
+  unsigned* partial = reinterpret_cast<unsigned*>(base + sc.off_partial);
+  unsigned* key = reinterpret_cast<unsigned*>(base + sc.off_key);
+  unsigned* rank = reinterpret_cast<unsigned*>(base + sc.off_rank);
+  unsigned* perm = reinterpret_cast<unsigned*>(base + sc.off_perm);
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(sc.nkeys)), dim3(256), 0, st, count,
+                     static_cast<long long>(sc.nkeys), 0u);
+  if (sc.split)
+    hipLaunchKernelGGL((k_sched_keys<SP, true>), dim3(grid_of(sc.items)), dim3(256), 0, st, v->vol, sc.g, x,
+                       sc.items, count, key, rank);
   else
-    hipLaunchKernelGGL((k_eval<SP, CT, AT, false>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, x,
-                       static_cast<long long>(n), static_cast<AT*>(f), static_cast<AT*>(grad));
+    hipLaunchKernelGGL((k_sched_keys<SP, false>), dim3(grid_of(sc.items)), dim3(256), 0, st, v->vol, sc.g, x,
+                       sc.items, count, key, rank);
+  const unsigned nblocks = (sc.nkeys + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(256), 0, st, count, offset, partial, sc.nkeys);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, partial, nblocks);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(256), 0, st, offset, partial, sc.nkeys);
+  hipLaunchKernelGGL(k_sched_scatter, dim3(grid_of(sc.items)), dim3(256), 0, st, sc.items, key, rank, offset, perm);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
 template <class SP>
-lsp_status eval_spec(const lsp_vol_s* v, const float* x, int64_t n, void* f, void* grad, hipStream_t st) {
+const unsigned* sched_perm(const lsp_vol_s* v, int64_t n, const void* ws, long long& items, bool& split) {
+  const Sched sc = make_sched<SP>(v, n);
+  items = sc.items;
+  split = sc.split;
+  return reinterpret_cast<const unsigned*>(static_cast<const char*>(ws) + sc.off_perm);
+}
+
+template <class SP, class CT, class AT>
+lsp_status launch_eval(const lsp_vol_s* v, const float* x, int64_t n, const void* ws, void* f, void* grad,
+                       hipStream_t st) {
+  AT* fo = static_cast<AT*>(f);
+  AT* go = static_cast<AT*>(grad);
+  if (!ws) {
+    if (grad)
+      hipLaunchKernelGGL((k_eval<SP, CT, AT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
+                         static_cast<long long>(n), nullptr, fo, go);
+    else
+      hipLaunchKernelGGL((k_eval<SP, CT, AT, false, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
+                         static_cast<long long>(n), nullptr, fo, go);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+  }
+  long long items;
+  bool split;
+  const unsigned* perm = sched_perm<SP>(v, n, ws, items, split);
+  if (split) {
+    hipLaunchKernelGGL((k_fill_zero<AT>), dim3(fill_grid(n)), dim3(256), 0, st, fo, static_cast<long long>(n));
+    if (grad) {
+      hipLaunchKernelGGL((k_fill_zero<AT>), dim3(fill_grid(n * SP::S)), dim3(256), 0, st, go,
+                         static_cast<long long>(n * SP::S));
+      hipLaunchKernelGGL((k_eval<SP, CT, AT, true, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
+                         items, perm, fo, go);
+    } else {
+      hipLaunchKernelGGL((k_eval<SP, CT, AT, false, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
+                         items, perm, fo, go);
+    }
+  } else {
+    if (grad)
+      hipLaunchKernelGGL((k_eval<SP, CT, AT, true, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
+                         items, perm, fo, go);
+    else
+      hipLaunchKernelGGL((k_eval<SP, CT, AT, false, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
+                         items, perm, fo, go);
+  }
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+template <class SP>
+lsp_status eval_spec(const lsp_vol_s* v, const float* x, int64_t n, const void* ws, void* f, void* grad,
+                     hipStream_t st) {
   switch (v->dtype) {
-    case LSP_F32: return launch_eval<SP, float, float>(v, x, n, f, grad, st);
-    case LSP_BF16: return launch_eval<SP, bf16_t, float>(v, x, n, f, grad, st);
-    case LSP_F16: return launch_eval<SP, f16_t, float>(v, x, n, f, grad, st);
-    case LSP_F64: return launch_eval<SP, double, double>(v, x, n, f, grad, st);
+    case LSP_F32: return launch_eval<SP, float, float>(v, x, n, ws, f, grad, st);
+    case LSP_BF16: return launch_eval<SP, bf16_t, float>(v, x, n, ws, f, grad, st);
+    case LSP_F16: return launch_eval<SP, f16_t, float>(v, x, n, ws, f, grad, st);
+    case LSP_F64: return launch_eval<SP, double, double>(v, x, n, ws, f, grad, st);
   }
   return LSP_ERR_DTYPE;
 }
 
 template <class SP, class CT>
-lsp_status launch_mse(const lsp_vol_s* v, const float* x, const float* y, int64_t n, float* f, float* dldf,
-                      double* loss, hipStream_t st) {
-  const int block = 256;
-  const long long grid = (n + block - 1) / block;
-  hipLaunchKernelGGL((k_eval_mse<SP, CT>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, x, y,
-                     static_cast<long long>(n), 1.0f / static_cast<float>(n), f, dldf, loss);
+lsp_status launch_mse(const lsp_vol_s* v, const float* x, const float* y, int64_t n, const void* ws, float* f,
+                      float* dldf, double* loss, hipStream_t st) {
+  const float inv_n = 1.0f / static_cast<float>(n);
+  long long items = n;
+  bool split = false;
+  const unsigned* perm = ws ? sched_perm<SP>(v, n, ws, items, split) : nullptr;
+  if (!split) {
+    hipLaunchKernelGGL((k_eval_mse<SP, CT>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x, y,
+                       static_cast<long long>(n), perm, inv_n, f, dldf, loss);
+  } else {
+    hipLaunchKernelGGL((k_fill_zero<float>), dim3(fill_grid(n)), dim3(256), 0, st, f, static_cast<long long>(n));
+    hipLaunchKernelGGL((k_eval<SP, CT, float, false, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
+                       items, perm, f, static_cast<float*>(nullptr));
+    hipLaunchKernelGGL(k_mse_head, dim3(grid_of(n)), dim3(256), 0, st, f, y, static_cast<long long>(n), inv_n, dldf,
+                       loss);
+  }
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
 template <class SP>
-lsp_status mse_spec(const lsp_vol_s* v, const float* x, const float* y, int64_t n, float* f, float* dldf,
-                    double* loss, hipStream_t st) {
+lsp_status mse_spec(const lsp_vol_s* v, const float* x, const float* y, int64_t n, const void* ws, float* f,
+                    float* dldf, double* loss, hipStream_t st) {
   switch (v->dtype) {
-    case LSP_F32: return launch_mse<SP, float>(v, x, y, n, f, dldf, loss, st);
-    case LSP_BF16: return launch_mse<SP, bf16_t>(v, x, y, n, f, dldf, loss, st);
-    case LSP_F16: return launch_mse<SP, f16_t>(v, x, y, n, f, dldf, loss, st);
+    case LSP_F32: return launch_mse<SP, float>(v, x, y, n, ws, f, dldf, loss, st);
+    case LSP_BF16: return launch_mse<SP, bf16_t>(v, x, y, n, ws, f, dldf, loss, st);
+    case LSP_F16: return launch_mse<SP, f16_t>(v, x, y, n, ws, f, dldf, loss, st);
   }
   return LSP_ERR_DTYPE;
 }
 
 template <class SP, class CT>
-lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_t n, float* const* grad_c,
-                      float* grad_x, hipStream_t st) {
+lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_t n, const void* ws,
+                      float* const* grad_c, float* grad_x, hipStream_t st) {
   GradVol gv{};
   for (int k = 0; k < SP::M; ++k) gv.base[k] = grad_c[k];
-  const int block = 256;
-  const long long grid = (n + block - 1) / block;
-  if (grad_x)
-    hipLaunchKernelGGL((k_adjoint<SP, CT, true>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, gv,
-                       x, g, static_cast<long long>(n), grad_x);
-  else
-    hipLaunchKernelGGL((k_adjoint<SP, CT, false>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol,
-                       gv, x, g, static_cast<long long>(n), grad_x);
+  long long items = n;
+  bool split = false;
+  const unsigned* perm = ws ? sched_perm<SP>(v, n, ws, items, split) : nullptr;
+  if (split) {
+    if (grad_x) {
+      hipLaunchKernelGGL((k_fill_zero<float>), dim3(fill_grid(n * SP::S)), dim3(256), 0, st, grad_x,
+                         static_cast<long long>(n * SP::S));
+      hipLaunchKernelGGL((k_adjoint<SP, CT, true, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x, g,
+                         items, perm, grad_x);
+    } else {
+      hipLaunchKernelGGL((k_adjoint<SP, CT, false, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x,
+                         g, items, perm, grad_x);
+    }
+  } else {
+    if (grad_x)
+      hipLaunchKernelGGL((k_adjoint<SP, CT, true, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x, g,
+                         items, perm, grad_x);
+    else
+      hipLaunchKernelGGL((k_adjoint<SP, CT, false, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x,
+                         g, items, perm, grad_x);
+  }
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
 template <class SP>
-lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t n, float* const* grad_c,
-                    float* grad_x, hipStream_t st) {
+lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t n, const void* ws,
+                    float* const* grad_c, float* grad_x, hipStream_t st) {
   switch (v->dtype) {
-    case LSP_F32: return launch_adj<SP, float>(v, x, g, n, grad_c, grad_x, st);
-    case LSP_BF16: return launch_adj<SP, bf16_t>(v, x, g, n, grad_c, grad_x, st);
-    case LSP_F16: return launch_adj<SP, f16_t>(v, x, g, n, grad_c, grad_x, st);
+    case LSP_F32: return launch_adj<SP, float>(v, x, g, n, ws, grad_c, grad_x, st);
+    case LSP_BF16: return launch_adj<SP, bf16_t>(v, x, g, n, ws, grad_c, grad_x, st);
+    case LSP_F16: return launch_adj<SP, f16_t>(v, x, g, n, ws, grad_c, grad_x, st);
   }
   return LSP_ERR_DTYPE;
+}
+
+template <class SP>
+lsp_status sched_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes) {
+  *bytes = make_sched<SP>(v, n).bytes;
+  return LSP_OK;
+}
+
+template <class SP>
+lsp_status sched_spec(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
+  return run_schedule<SP>(v, x, n, ws, st);
 }
 
 template <class SP, class CT>
@@ -401,7 +546,7 @@ lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void*
   if (!x || !f) return LSP_ERR_NULL;
   if (n > (int64_t(1) << 40)) return LSP_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, eval_spec, vol, x, n, f, grad_x, s)
+  LSP_DISPATCH(plan->spec, eval_spec, vol, x, n, nullptr, f, grad_x, s)
 }
 
 lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n, float* f,
@@ -413,7 +558,7 @@ lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float*
   if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, f, dloss_df, loss, s)
+  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, nullptr, f, dloss_df, loss, s)
 }
 
 lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
@@ -428,7 +573,7 @@ lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const fl
     if (!grad_c[k]) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, grad_c, grad_x, s)
+  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, nullptr, grad_c, grad_x, s)
 }
 
 lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
@@ -448,6 +593,78 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
   rp.W = W; rp.H = H; rp.steps = steps;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, rays_spec, vol, rp, ray0, nrays, out, samples, s)
+}
+
+static lsp_status check_ws(lsp_plan plan, lsp_vol vol, int64_t n, const void* ws, size_t ws_bytes) {
+  if (!ws) return LSP_ERR_NULL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return LSP_ERR_INVALID;
+  size_t need = 0;
+  lsp_status st = lsp_schedule_size(plan, vol, n, &need);
+  if (st != LSP_OK) return st;
+  return ws_bytes >= need ? LSP_OK : LSP_ERR_INVALID;
+}
+
+lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (!bytes) return LSP_ERR_NULL;
+  if (n < 0 || n * specs()[plan->spec].M >= (int64_t(1) << 32)) return LSP_ERR_INVALID;
+  LSP_DISPATCH(plan->spec, sched_size_spec, vol, n, bytes)
+}
+
+lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace, size_t ws_bytes,
+                        void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if (n == 0) return LSP_OK;
+  if (!x) return LSP_ERR_NULL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, sched_spec, vol, x, n, workspace, s)
+}
+
+lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
+                              size_t ws_bytes, void* f, void* grad_x, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if (n == 0) return LSP_OK;
+  if (!x || !f) return LSP_ERR_NULL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, eval_spec, vol, x, n, workspace, f, grad_x, s)
+}
+
+lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n,
+                                  const void* workspace, size_t ws_bytes, float* f, float* dloss_df, double* loss,
+                                  void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if (n == 0) return LSP_OK;
+  if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, workspace, f, dloss_df, loss, s)
+}
+
+lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
+                                      const void* workspace, size_t ws_bytes, float* const* grad_c, float* grad_x,
+                                      void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if (n == 0) return LSP_OK;
+  if (!x || !g || !grad_c) return LSP_ERR_NULL;
+  const SpecDesc& sd = specs()[plan->spec];
+  for (int k = 0; k < sd.M; ++k)
+    if (!grad_c[k]) return LSP_ERR_NULL;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, workspace, grad_c, grad_x, s)
 }
 
 }  // extern "C"

@@ -46,6 +46,25 @@ struct GradVol {
   float* base[kMaxCosets];
 };
 
+// Select coset k's pointer / shift with a compare chain: k may differ per lane
+// (coset-split work items), and a lane-indexed kernel-argument array would be
+// copied to scratch memory.
+template <int M, class P>
+__device__ __forceinline__ P pick(const P* arr, int k) {
+  P p = arr[0];
+#pragma unroll
+  for (int j = 1; j < M; ++j) p = (k == j) ? arr[j] : p;
+  return p;
+}
+
+template <class SP>
+__device__ __forceinline__ int coset_shift(int k, int d) {
+  int v = SP::SHIFT[0][d];
+#pragma unroll
+  for (int j = 1; j < SP::M; ++j) v = (k == j) ? SP::SHIFT[j][d] : v;
+  return v;
+}
+
 // ----------------------------------------------------------------------------
 // coefficient storage types
 struct bf16_t { uint16_t v; };
@@ -83,11 +102,11 @@ __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, F
   bool interior = true;
 #pragma unroll
   for (int d = 0; d < S; ++d) {
-    AT xp = x[d] - AT(SP::SHIFT[k][d]);
+    AT xp = x[d] - AT(coset_shift<SP>(k, d));
     AT fl = afloor<AT>(xp * AT(1.0 / SP::D));
     // keep the index arithmetic in range for huge or non-finite queries
     fl = fl > AT(1 << 24) ? AT(1 << 24) : (fl < AT(-(1 << 24)) ? AT(-(1 << 24)) : fl);
-    int id = static_cast<int>(fl);
+    int id = (fl == fl) ? static_cast<int>(fl) : 0;   // NaN queries: any in-range cell
     AT u = (xp - AT(SP::D) * fl) - AT(0.5 * SP::D);
     F.i[d] = id;
     interior = interior && (id + SP::OMIN >= 0) && (id + SP::OMAX < vol.dims[d]);
@@ -133,7 +152,7 @@ struct Gather {
   int jlo[SP::S], jhi[SP::S];  // CHECK: valid J range per folded axis
 
   __device__ __forceinline__ void init(const Vol& vol, int k, const Folded<SP, AT>& F) {
-    const CT* base = static_cast<const CT*>(vol.base[k]);
+    const CT* base = static_cast<const CT*>(pick<SP::M>(vol.base, k));
     safe = base;
     long long off = 0;
 #pragma unroll
@@ -276,13 +295,76 @@ __device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* x
   }
 }
 
+// adjoint of one coset: scatter g * w_j into the gradient volume, and (GRADX)
+// accumulate the folded-frame gradient of psi mapped back to x
+template <class SP, class CT, bool GRADX>
+__device__ __forceinline__ void coset_adjoint(const Vol& vol, const GradVol& gvol, int k, const float* xq,
+                                              float gq, float* gx) {
+  Folded<SP, float> F;
+  fold_query<SP, float>(xq, k, vol, F);
+  const int ob = SP::template orbit<float>(F.up);
+  float mono[SP::NMON];
+  monomials<SP, float>(F.up, mono);
+  float* gbase = pick<SP::M>(gvol.base, k);
+  if (F.interior) {
+    Scatter<SP, false> sc;
+    sc.init(vol, gbase, F, gq);
+    SP::template w_any<float>(ob, sc, mono);
+  } else {
+    Scatter<SP, true> sc;
+    sc.init(vol, gbase, F, gq);
+    SP::template w_any<float>(ob, sc, mono);
+  }
+  if constexpr (GRADX) {
+    float b[SP::NMON];
+    if (F.interior) {
+      Gather<SP, CT, float, false> g;
+      g.init(vol, k, F);
+      SP::template b_any<float>(ob, g, b);
+    } else {
+      Gather<SP, CT, float, true> g;
+      g.init(vol, k, F);
+      SP::template b_any<float>(ob, g, b);
+    }
+    float dpsi[SP::S];
+    (void)poly_eval<SP, float, true>(b, mono, dpsi);
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const float v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : 0.f;
+    }
+  }
+}
+
 // ----------------------------------------------------------------------------
-// forward: f (and grad) at N queries, x as N x S float32 (row-major)
-template <class SP, class CT, class AT, bool GRAD>
-__global__ void __launch_bounds__(256) k_eval(Vol vol, const float* __restrict__ x, long long n,
-                                              AT* __restrict__ f, AT* __restrict__ grad) {
-  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= n) return;
+// Work items.  Without a schedule item t is query t.  With a schedule
+// (counting sort, below) perm[t] names the item: a query (all cosets in one
+// lane), or, when the spline has several sub-regions (SPLIT), one
+// (query, coset) pair q * M + k, so that a wave holds one sub-region.
+template <class SP, bool SPLIT>
+__device__ __forceinline__ void item_of(long long t, const unsigned* perm, long long& q, int& k) {
+  const long long it = perm ? static_cast<long long>(perm[t]) : t;
+  if constexpr (SPLIT) {
+    q = it / SP::M;
+    k = static_cast<int>(it - q * SP::M);
+  } else {
+    q = it;
+    k = 0;
+  }
+}
+
+// forward: f (and grad) at N queries, x as N x S float32 (row-major).
+// SPLIT: f and grad must be zero on entry; lanes add their coset's share.
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT>
+__global__ void __launch_bounds__(256) k_eval(Vol vol, const float* __restrict__ x, long long n_items,
+                                              const unsigned* __restrict__ perm, AT* __restrict__ f,
+                                              AT* __restrict__ grad) {
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  long long q;
+  int k;
+  item_of<SP, SPLIT>(t, perm, q, k);
   AT xq[SP::S];
 #pragma unroll
   for (int d = 0; d < SP::S; ++d) xq[d] = static_cast<AT>(x[q * SP::S + d]);
@@ -290,49 +372,82 @@ __global__ void __launch_bounds__(256) k_eval(Vol vol, const float* __restrict__
   AT gx[SP::S];
 #pragma unroll
   for (int d = 0; d < SP::S; ++d) gx[d] = AT(0);
+  if constexpr (SPLIT) {
+    coset_contrib<SP, CT, AT, GRAD>(vol, k, xq, acc, gx);
+    atomicAdd(f + q, acc);
+    if constexpr (GRAD) {
 #pragma unroll
-  for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, AT, GRAD>(vol, k, xq, acc, gx);
-  f[q] = acc;
-  if constexpr (GRAD) {
+      for (int d = 0; d < SP::S; ++d) atomicAdd(grad + q * SP::S + d, gx[d]);
+    }
+  } else {
 #pragma unroll
-    for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = gx[d];
+    for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, AT, GRAD>(vol, kk, xq, acc, gx);
+    f[q] = acc;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = gx[d];
+    }
   }
 }
 
-// forward with a mean-squared-error head: writes f, dL/df = 2 (f - y) / N and
-// accumulates L = sum (f - y)^2 / N into *loss (FP64 atomics, one per block)
-template <class SP, class CT>
-__global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restrict__ x, const float* __restrict__ y,
-                                                  long long n, float inv_n, float* __restrict__ f,
-                                                  float* __restrict__ dldf, double* __restrict__ loss) {
+// mean-squared-error head on a complete f: dL/df = 2 (f - y) / N, L += sum (f - y)^2 / N
+__device__ __forceinline__ void mse_reduce(float r2, double inv_n, double* loss) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, static_cast<double>(r2) * inv_n);
+}
+
+__global__ void __launch_bounds__(256) k_mse_head(const float* __restrict__ f, const float* __restrict__ y,
+                                                  long long n, float inv_n, float* __restrict__ dldf,
+                                                  double* __restrict__ loss) {
   const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   float r2 = 0.f;
   if (q < n) {
+    const float r = f[q] - y[q];
+    dldf[q] = 2.f * r * inv_n;
+    r2 = r * r;
+  }
+  mse_reduce(r2, static_cast<double>(inv_n), loss);
+}
+
+// forward fused with the MSE head (whole queries per lane)
+template <class SP, class CT>
+__global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restrict__ x, const float* __restrict__ y,
+                                                  long long n, const unsigned* __restrict__ perm, float inv_n,
+                                                  float* __restrict__ f, float* __restrict__ dldf,
+                                                  double* __restrict__ loss) {
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  float r2 = 0.f;
+  if (t < n) {
+    long long q;
+    int k;
+    item_of<SP, false>(t, perm, q, k);
     float xq[SP::S];
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
     float acc = 0.f;
     float gx[SP::S];
 #pragma unroll
-    for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, float, false>(vol, k, xq, acc, gx);
+    for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, float, false>(vol, kk, xq, acc, gx);
     const float r = acc - y[q];
     f[q] = acc;
     dldf[q] = 2.f * r * inv_n;
     r2 = r * r;
   }
-  // wave reduction, then one atomic per wave
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(loss, static_cast<double>(r2) * static_cast<double>(inv_n));
+  mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
 
-// adjoint: grad_c[site] += g_q * w_site(x_q) (scatter-add), grad_x = g_q * grad f
-template <class SP, class CT, bool GRADX>
+// adjoint: grad_c[site] += g_q * w_site(x_q) (scatter-add), grad_x = g_q * grad f.
+// SPLIT: grad_x must be zero on entry.
+template <class SP, class CT, bool GRADX, bool SPLIT>
 __global__ void __launch_bounds__(256) k_adjoint(Vol vol, GradVol gvol, const float* __restrict__ x,
-                                                 const float* __restrict__ gout, long long n,
-                                                 float* __restrict__ grad_x) {
-  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= n) return;
+                                                 const float* __restrict__ gout, long long n_items,
+                                                 const unsigned* __restrict__ perm, float* __restrict__ grad_x) {
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  long long q;
+  int k;
+  item_of<SP, SPLIT>(t, perm, q, k);
   float xq[SP::S];
 #pragma unroll
   for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
@@ -340,47 +455,159 @@ __global__ void __launch_bounds__(256) k_adjoint(Vol vol, GradVol gvol, const fl
   float gx[SP::S];
 #pragma unroll
   for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
+  if constexpr (SPLIT) {
+    coset_adjoint<SP, CT, GRADX>(vol, gvol, k, xq, gq, gx);
+    if constexpr (GRADX) {
 #pragma unroll
-  for (int k = 0; k < SP::M; ++k) {
+      for (int d = 0; d < SP::S; ++d) atomicAdd(grad_x + q * SP::S + d, gq * gx[d]);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < SP::M; ++kk) coset_adjoint<SP, CT, GRADX>(vol, gvol, kk, xq, gq, gx);
+    if constexpr (GRADX) {
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) grad_x[q * SP::S + d] = gq * gx[d];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Query schedule: a counting sort of the work items by key
+//   key = (sub-region, Morton index of the item's brick of cells)
+// (sub-region only for SPLIT items).  Items of one brick then run in the same
+// waves, so their stencils overlap in the L1/L2 caches, and SPLIT waves hold a
+// single sub-region, so the sub-region branch does not diverge.
+struct SchedGeom {
+  int bshift;           // brick = cell >> bshift per axis
+  int nbits;            // Morton bits per axis
+  int nb[kMaxDim];      // bricks per axis
+};
+
+template <class SP>
+__device__ __forceinline__ unsigned morton_key(const int* b, int nbits) {
+  unsigned code = 0;
+  for (int bit = 0; bit < nbits; ++bit) {
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) code |= static_cast<unsigned>((b[d] >> bit) & 1) << (bit * SP::S + d);
+  }
+  return code;
+}
+
+template <class SP, bool SPLIT>
+__global__ void __launch_bounds__(256) k_sched_keys(Vol vol, SchedGeom g, const float* __restrict__ x,
+                                                    long long n_items, unsigned* __restrict__ count,
+                                                    unsigned* __restrict__ key, unsigned* __restrict__ rank) {
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  long long q;
+  int k;
+  item_of<SP, SPLIT>(t, nullptr, q, k);
+  float xq[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
+  int b[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) {
+    float fl = floorf((xq[d] - static_cast<float>(coset_shift<SP>(k, d))) * (1.0f / SP::D));
+    fl = fl > 1e7f ? 1e7f : (fl < -1e7f ? -1e7f : fl);
+    const int i = (fl == fl) ? static_cast<int>(fl) : 0;
+    int bb = i >> g.bshift;
+    bb = bb < 0 ? 0 : (bb >= g.nb[d] ? g.nb[d] - 1 : bb);
+    b[d] = bb;
+  }
+  unsigned kk = morton_key<SP>(b, g.nbits);
+  if constexpr (SPLIT) {
     Folded<SP, float> F;
     fold_query<SP, float>(xq, k, vol, F);
-    const int ob = SP::template orbit<float>(F.up);
-    float mono[SP::NMON];
-    monomials<SP, float>(F.up, mono);
-    if (F.interior) {
-      Scatter<SP, false> sc;
-      sc.init(vol, gvol.base[k], F, gq);
-      SP::template w_any<float>(ob, sc, mono);
-    } else {
-      Scatter<SP, true> sc;
-      sc.init(vol, gvol.base[k], F, gq);
-      SP::template w_any<float>(ob, sc, mono);
-    }
-    if constexpr (GRADX) {
-      float b[SP::NMON];
-      if (F.interior) {
-        Gather<SP, CT, float, false> g;
-        g.init(vol, k, F);
-        SP::template b_any<float>(ob, g, b);
-      } else {
-        Gather<SP, CT, float, true> g;
-        g.init(vol, k, F);
-        SP::template b_any<float>(ob, g, b);
-      }
-      float dpsi[SP::S];
-      (void)poly_eval<SP, float, true>(b, mono, dpsi);
-#pragma unroll
-      for (int r = 0; r < SP::S; ++r) {
-        const float v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
-#pragma unroll
-        for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : 0.f;
-      }
-    }
+    kk += static_cast<unsigned>(SP::template orbit<float>(F.up)) << (g.nbits * SP::S);
   }
-  if constexpr (GRADX) {
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) grad_x[q * SP::S + d] = gq * gx[d];
+  key[t] = kk;
+  rank[t] = atomicAdd(count + kk, 1u);
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(unsigned* __restrict__ p, long long n, unsigned v) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_fill_zero(T* __restrict__ p, long long n) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    p[i] = T(0);
+}
+
+// exclusive scan, three launches: per-1024 block scans, a scan of the block
+// totals (at most 1024 blocks), and the block offsets added back
+constexpr int kScanBlock = 1024;
+
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* lds, unsigned& total) {
+  // 256 threads
+  const int tid = threadIdx.x;
+  lds[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    unsigned add = tid >= off ? lds[tid - off] : 0u;
+    __syncthreads();
+    lds[tid] += add;
+    __syncthreads();
   }
+  total = lds[255];
+  const unsigned incl = lds[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(256) k_scan_blocks(const unsigned* __restrict__ in, unsigned* __restrict__ out,
+                                                     unsigned* __restrict__ partial, unsigned n) {
+  __shared__ unsigned lds[256];
+  const unsigned base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+  unsigned v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = (base + j < n) ? in[base + j] : 0u;
+  const unsigned sum = v[0] + v[1] + v[2] + v[3];
+  unsigned total;
+  unsigned run = block_exclusive_scan(sum, lds, total);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(256) k_scan_top(unsigned* __restrict__ partial, unsigned nblocks) {
+  __shared__ unsigned lds[256];
+  const unsigned base = threadIdx.x * 4;
+  unsigned v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = (base + j < nblocks) ? partial[base + j] : 0u;
+  unsigned total;
+  unsigned run = block_exclusive_scan(v[0] + v[1] + v[2] + v[3], lds, total);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < nblocks) partial[base + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(unsigned* __restrict__ out, const unsigned* __restrict__ partial,
+                                                  unsigned n) {
+  const unsigned add = partial[blockIdx.x];
+  const unsigned base = blockIdx.x * kScanBlock + threadIdx.x * 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (base + j < n) out[base + j] += add;
+}
+
+__global__ void __launch_bounds__(256) k_sched_scatter(long long n_items, const unsigned* __restrict__ key,
+                                                       const unsigned* __restrict__ rank,
+                                                       const unsigned* __restrict__ offset,
+                                                       unsigned* __restrict__ perm) {
+  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n_items) return;
+  perm[offset[key[t]] + rank[t]] = static_cast<unsigned>(t);
 }
 
 // Ray-marched samples (orthographic): sample (ray r, step j) is at

@@ -111,3 +111,23 @@ def test_bind_and_eval_argument_errors():
     L.lsp_vol_release(v)
     L.lsp_plan_destroy(p)
     L.lsp_plan_destroy(q)
+
+
+def test_schedule_workspace_checks():
+    L = _lib()
+    cfg = W.get("c5")
+    p = L.lsp_plan_create(cfg.L, cfg.Xi)
+    v = L.lsp_vol_bind(p, 0, [0x1000, 0x2000], (48, 48, 48, 48))
+    need = L.lsp_schedule_size(p, v, 1 << 22)
+    # items = queries x cosets for a spline with several sub-regions: 3 x 4 B each at least
+    assert need >= 12 * 2 * (1 << 22)
+    lib = L.lib()
+    assert lib.lsp_schedule(p, v, 0x1000, 1 << 22, 0x100000, need - 1, None) == -2      # too small
+    assert lib.lsp_schedule(p, v, 0x1000, 1 << 22, 0x100010, need, None) == -2          # misaligned
+    assert lib.lsp_schedule(p, v, 0x1000, 1 << 22, None, need, None) == -1
+    assert lib.lsp_eval_scheduled(p, v, 0x1000, 1 << 22, 0x100000, need - 1, 0x1000, None, None) == -2
+    assert lib.lsp_schedule(p, v, None, 0, 0x100000, L.lsp_schedule_size(p, v, 0), None) == 0   # empty batch
+    with pytest.raises(L.LspError):
+        L.lsp_schedule_size(p, v, 1 << 31)          # items would overflow 32 bits
+    L.lsp_vol_release(v)
+    L.lsp_plan_destroy(p)

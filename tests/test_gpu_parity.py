@@ -260,3 +260,70 @@ def test_full_size_sampled_c2(lsp):
     want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
     assert normwise(f[idx], want, coeffs) <= 1e-5
     assert np.all(np.isfinite(f))
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+def test_scheduled_order(lsp, name):
+    """The counting-sort schedule changes only the evaluation order: results
+    equal the given-order ones (bitwise for one sub-region; up to the order of
+    the per-coset float additions otherwise) and the oracle."""
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, n=2503, seed=12)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    x = torch.from_numpy(X).cuda()
+    grad = name != "c1"
+    r0 = sp.eval(vol, x, grad=grad)
+    sch = sp.schedule(vol, x)
+    r1 = sp.eval(vol, x, grad=grad, schedule=sch)
+    f0, f1 = (r0[0], r1[0]) if grad else (r0, r1)
+    split = sp.info["n_subregions"] > 1
+    if split:
+        assert normwise(f1.cpu().numpy(), f0.cpu().numpy(), coeffs) <= 1e-6
+    else:
+        assert torch.equal(f0, f1)
+    if grad:
+        assert normwise(r1[1].cpu().numpy(), r0[1].cpu().numpy(), coeffs) <= 1e-6
+    c32 = [c.astype(np.float32).astype(np.float64) for c in coeffs]
+    assert normwise(f1.cpu().numpy(), o.eval(c32, X.astype(np.float64)), coeffs) <= 1e-5
+    # adjoint through the same schedule
+    g = torch.from_numpy(np.random.default_rng(13).normal(size=len(X)).astype(np.float32)).cuda()
+    ga, gxa = sp.adjoint(vol, x, g, grad_x=True)
+    gb, gxb = sp.adjoint(vol, x, g, grad_x=True, schedule=sch)
+    for a, b in zip(ga, gb):
+        assert float((a - b).abs().max()) <= 1e-5 * max(1.0, float(a.abs().max()))
+    assert float((gxa - gxb).abs().max()) <= 1e-5 * max(1.0, float(gxa.abs().max()))
+    # MSE head through the schedule
+    if cfg.s == 3 or name == "c5":
+        y = torch.from_numpy(I.targets(cfg, X)).cuda()
+        fa, da, la = sp.eval_mse(vol, x, y)
+        fb, db, lb = sp.eval_mse(vol, x, y, schedule=sch)
+        assert float((fa - fb).abs().max()) <= 1e-6
+        assert float((da - db).abs().max()) <= 1e-9
+        assert abs(float(la) - float(lb)) <= 1e-6 * max(1.0, abs(float(la)))
+
+
+def test_scheduled_full_size_sampled(lsp):
+    """c5 at its full size through the schedule (the benchmark's launch), on
+    sampled outputs against the oracle; the adjoint's total mass is checked
+    against the forward by the adjoint identity <A c, g> = <c, A^T g>."""
+    torch = _torch()
+    cfg = W.get("c5")
+    coeffs = I.coefficients(cfg)
+    X = I.queries(cfg)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    dev = to_dev(coeffs, torch.float32)
+    vol = sp.bind(dev)
+    x = torch.from_numpy(X).cuda()
+    sch = sp.schedule(vol, x)
+    f = sp.eval(vol, x, schedule=sch)
+    idx = np.random.default_rng(14).choice(len(X), 512, replace=False)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
+    assert normwise(f.cpu().numpy()[idx], want, coeffs) <= 1e-5
+    g = torch.from_numpy(np.random.default_rng(15).normal(size=len(X)).astype(np.float32)).cuda()
+    gc, _ = sp.adjoint(vol, x, g, schedule=sch)
+    lhs = float(torch.dot(f.double(), g.double()))
+    rhs = float(sum(torch.sum(c.double() * a.double()) for c, a in zip(dev, gc)))
+    assert abs(lhs - rhs) <= 1e-4 * (abs(lhs) + float(g.abs().sum()) * 1e-3)
