@@ -136,11 +136,15 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
  * read neighbouring coefficients makes the stencil gathers hit the caches
  * (the paper notes that combining the reads of a coset exploits data
  * locality, Sec. 4).  lsp_schedule computes that order with a counting sort
- * on the GPU: key = Morton index of the query's brick of cells (8^3 cells in
- * 3-D, 4^4 in 4-D, coarser for volumes above 2^20 keys) and, for splines
- * with several sub-regions after the fold, the sub-region -- then one item is
- * one (query, coset) pair, so a wave evaluates one polynomial set instead of
- * all of them (the branch predication of Sec. 4.3 is avoided).
+ * on the GPU (per-tile LDS histograms, a scan, and a placement pass that
+ * writes each query's record to its sorted position): key = brick of cells
+ * (8^s cells, coarser when there would be more than 16384 keys) and, for
+ * splines whose several sub-regions carry costly polynomials, the
+ * sub-region -- an item is then one (query, coset) pair, so a wave evaluates
+ * one polynomial set instead of predicating all of them (Sec. 4.3).  The
+ * scheduled calls run one workgroup per brick, which (in 3-D) stages the
+ * brick's coefficients plus the stencil halo in LDS; the adjoint accumulates
+ * its scatter-add in LDS and flushes it once per brick.
  *
  * lsp_schedule_size: device workspace bytes for n queries (depends on the
  * plan, the volume dims and n).  lsp_schedule: fills that caller-owned,
@@ -148,8 +152,8 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
  * *_scheduled calls then evaluate the same x (same n) in that order; results
  * land at each query's own index, exactly as the unscheduled calls.
  * Errors: LSP_ERR_NULL, LSP_ERR_INVALID (workspace too small or misaligned,
- * n * cosets >= 2^32).  With several sub-regions, f and grad_x are
- * accumulated with float atomics over the cosets (summation order not fixed). */
+ * n * cosets >= 2^32).  The adjoint's float additions into grad_c happen in
+ * an unspecified order (LDS and global atomics). */
 lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes);
 lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace, size_t ws_bytes,
                         void* stream);

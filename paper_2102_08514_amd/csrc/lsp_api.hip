@@ -13,6 +13,7 @@
 
 #include "../../include/lsp.h"
 #include "lsp_kernels.hip"
+#include "lsp_binned.hip"
 
 namespace {
 
@@ -127,87 +128,123 @@ std::vector<int> canon_dir(std::vector<int> v) {
 }
 
 // ---------------------------------------------------------------------------
-// schedule geometry and workspace layout (all uint32):
-//   count[nkeys] offset[nkeys] partial[1024] key[items] rank[items] perm[items]
-struct Sched {
+// binned schedule: geometry and workspace layout (bytes, 256-aligned):
+//   hist[tiles][nkeys] tot[nkeys+1] start[nkeys+1] partial[1024] recs[items]
+//   fpart[items] gpart[items][S]   (partials only for coset-split items)
+constexpr size_t kLdsBudget = 65536;   // per workgroup
+
+struct Bin {
+  BinGeom g;
   bool split;
-  long long items;
-  SchedGeom g;
-  unsigned nkeys;
-  size_t off_count, off_offset, off_partial, off_key, off_rank, off_perm, bytes;
+  int at_size;
+  size_t off_hist, off_tot, off_start, off_partial, off_recs, off_fpart, off_gpart, bytes;
+  size_t lds_eval, lds_adj;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
-
-template <class SP>
-Sched make_sched(const lsp_vol_s* v, int64_t n) {
-  Sched sc{};
-  sc.split = SP::K > 1;
-  sc.items = sc.split ? n * SP::M : n;
-  int bshift = SP::S == 3 ? 3 : 2;
-  for (;;) {
-    int maxnb = 1;
-    for (int d = 0; d < SP::S; ++d) {
-      sc.g.nb[d] = ((v->vol.dims[d] + (1 << bshift) - 1) >> bshift) + 1;
-      maxnb = std::max(maxnb, sc.g.nb[d]);
-    }
-    int nbits = 0;
-    while ((1 << nbits) < maxnb) ++nbits;
-    const unsigned long long nkeys = static_cast<unsigned long long>(sc.split ? SP::K : 1) << (nbits * SP::S);
-    if (nkeys <= (1ull << 20)) {
-      sc.g.bshift = bshift;
-      sc.g.nbits = nbits;
-      sc.nkeys = static_cast<unsigned>(nkeys);
-      break;
-    }
-    ++bshift;
-  }
-  size_t o = 0;
-  sc.off_count = o; o = align256(o + 4ull * sc.nkeys);
-  sc.off_offset = o; o = align256(o + 4ull * sc.nkeys);
-  sc.off_partial = o; o = align256(o + 4ull * 1024);
-  sc.off_key = o; o = align256(o + 4ull * sc.items);
-  sc.off_rank = o; o = align256(o + 4ull * sc.items);
-  sc.off_perm = o; o = align256(o + 4ull * sc.items);
-  sc.bytes = o;
-  return sc;
-}
-
 unsigned grid_of(long long n, int block = 256) { return static_cast<unsigned>((n + block - 1) / block); }
 unsigned fill_grid(long long n) { return static_cast<unsigned>(std::min<long long>((n + 255) / 256, 4096)); }
 
 template <class SP>
-lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
-  const Sched sc = make_sched<SP>(v, n);
-  char* base = static_cast<char*>(ws);
-  unsigned* count = reinterpret_cast<unsigned*>(base + sc.off_count);
-  unsigned* offset = reinterpret_cast<unsigned*>(base + sc.off_offset);
-  unsigned* partial = reinterpret_cast<unsigned*>(base + sc.off_partial);
-  unsigned* key = reinterpret_cast<unsigned*>(base + sc.off_key);
-  unsigned* rank = reinterpret_cast<unsigned*>(base + sc.off_rank);
-  unsigned* perm = reinterpret_cast<unsigned*>(base + sc.off_perm);
-  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(sc.nkeys)), dim3(256), 0, st, count,
-                     static_cast<long long>(sc.nkeys), 0u);
-  if (sc.split)
-    hipLaunchKernelGGL((k_sched_keys<SP, true>), dim3(grid_of(sc.items)), dim3(256), 0, st, v->vol, sc.g, x,
-                       sc.items, count, key, rank);
-  else
-    hipLaunchKernelGGL((k_sched_keys<SP, false>), dim3(grid_of(sc.items)), dim3(256), 0, st, v->vol, sc.g, x,
-                       sc.items, count, key, rank);
-  const unsigned nblocks = (sc.nkeys + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(256), 0, st, count, offset, partial, sc.nkeys);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, partial, nblocks);
-  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(256), 0, st, offset, partial, sc.nkeys);
-  hipLaunchKernelGGL(k_sched_scatter, dim3(grid_of(sc.items)), dim3(256), 0, st, sc.items, key, rank, offset, perm);
-  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+Bin make_bin(const lsp_vol_s* v, int64_t n) {
+  Bin bn{};
+  bn.split = SplitPolicy<SP>::value;
+  bn.at_size = v->dtype == LSP_F64 ? 8 : 4;
+  BinGeom& g = bn.g;
+  g.n = n;
+  g.items = bn.split ? n * SP::M : n;
+  g.kpb = bn.split ? SP::K : 1;
+  for (g.bshift = 3;; ++g.bshift) {
+    unsigned long long nbr = 1;
+    for (int d = 0; d < SP::S; ++d) {
+      g.nb[d] = (v->vol.dims[d] + (1 << g.bshift) - 1) >> g.bshift;
+      nbr *= static_cast<unsigned long long>(g.nb[d]);
+    }
+    if (nbr * g.kpb * 4 <= kLdsBudget) {
+      g.nbricks = static_cast<unsigned>(nbr);
+      g.nkeys = static_cast<unsigned>(nbr * g.kpb);
+      break;
+    }
+  }
+  g.tiles = static_cast<int>(std::max<long long>(1, std::min<long long>(256, (g.items + 4095) / 4096)));
+  g.tile_items = (g.items + g.tiles - 1) / g.tiles;
+  size_t o = 0;
+  bn.off_hist = o; o = align256(o + 4ull * g.tiles * g.nkeys);
+  bn.off_tot = o; o = align256(o + 4ull * (g.nkeys + 1));
+  bn.off_start = o; o = align256(o + 4ull * (g.nkeys + 1));
+  bn.off_partial = o; o = align256(o + 4ull * 1024);
+  bn.off_recs = o; o = align256(o + sizeof(Rec<SP::S>) * static_cast<size_t>(g.items));
+  bn.off_fpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items : 0));
+  bn.off_gpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items * SP::S : 0));
+  bn.bytes = o;
+  const size_t region = SP::S == 3 ? static_cast<size_t>(SP::M) * Staged<SP>::volume(1 << g.bshift) : 0;
+  bn.lds_eval = region * bn.at_size;
+  bn.lds_adj = region * 4 * 2;
+  return bn;
 }
 
 template <class SP>
-const unsigned* sched_perm(const lsp_vol_s* v, int64_t n, const void* ws, long long& items, bool& split) {
-  const Sched sc = make_sched<SP>(v, n);
-  items = sc.items;
-  split = sc.split;
-  return reinterpret_cast<const unsigned*>(static_cast<const char*>(ws) + sc.off_perm);
+lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
+  const Bin bn = make_bin<SP>(v, n);
+  const BinGeom& g = bn.g;
+  char* base = static_cast<char*>(ws);
+  unsigned* hist = reinterpret_cast<unsigned*>(base + bn.off_hist);
+  unsigned* tot = reinterpret_cast<unsigned*>(base + bn.off_tot);
+  unsigned* start = reinterpret_cast<unsigned*>(base + bn.off_start);
+  unsigned* partial = reinterpret_cast<unsigned*>(base + bn.off_partial);
+  Rec<SP::S>* recs = reinterpret_cast<Rec<SP::S>*>(base + bn.off_recs);
+  const size_t lds = 4ull * g.nkeys;
+  constexpr bool SPLIT = SplitPolicy<SP>::value;
+  hipLaunchKernelGGL((k_bin_hist<SP, SPLIT>), dim3(g.tiles), dim3(1024), lds, st, v->vol, g, x, hist);
+  hipLaunchKernelGGL(k_bin_colscan, dim3(grid_of(g.nkeys + 1)), dim3(256), 0, st, hist, g.tiles, g.nkeys, tot);
+  const unsigned nscan = g.nkeys + 1;
+  const unsigned nblocks = (nscan + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nblocks), dim3(256), 0, st, tot, start, partial, nscan);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, st, partial, nblocks);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblocks), dim3(256), 0, st, start, partial, nscan);
+  hipLaunchKernelGGL((k_bin_place<SP, SPLIT>), dim3(g.tiles), dim3(1024), lds, st, v->vol, g, x, hist, start,
+                     recs);
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+unsigned brick_grid(unsigned nbricks) { return 8u * ((nbricks + 7u) / 8u); }
+
+template <class SP, class CT, class AT, bool MSE>
+lsp_status launch_binned_eval(const lsp_vol_s* v, const float* x, int64_t n, const void* ws, AT* f, AT* grad,
+                              const float* y, float* dldf, double* loss, hipStream_t st) {
+  (void)x;
+  const Bin bn = make_bin<SP>(v, n);
+  const BinGeom& g = bn.g;
+  const char* base = static_cast<const char*>(ws);
+  const unsigned* start = reinterpret_cast<const unsigned*>(base + bn.off_start);
+  const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
+  constexpr bool SPLIT = SplitPolicy<SP>::value;
+  constexpr bool STAGE = SP::S == 3;
+  const float inv_n = 1.0f / static_cast<float>(n);
+  if (bn.lds_eval > kLdsBudget) return LSP_ERR_UNSUPPORTED;
+  if constexpr (SPLIT) {
+    AT* fpart = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_fpart);
+    AT* gpart = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_gpart);
+    if (grad) {
+      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, true, true, STAGE, false>), dim3(brick_grid(g.nbricks)),
+                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, fpart, gpart, y, inv_n, dldf, loss);
+      hipLaunchKernelGGL((k_combine<SP, AT, true, false>), dim3(std::min(grid_of(n), 1024u)), dim3(256), 0, st, fpart, gpart,
+                         static_cast<long long>(n), f, grad, y, inv_n, dldf, loss);
+    } else {
+      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, false, true, STAGE, false>), dim3(brick_grid(g.nbricks)),
+                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, fpart, gpart, y, inv_n, dldf, loss);
+      hipLaunchKernelGGL((k_combine<SP, AT, false, MSE>), dim3(std::min(grid_of(n), 1024u)), dim3(256), 0, st, fpart, gpart,
+                         static_cast<long long>(n), f, grad, y, inv_n, dldf, loss);
+    }
+  } else {
+    if (grad)
+      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, true, false, STAGE, false>), dim3(brick_grid(g.nbricks)),
+                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, f, grad, y, inv_n, dldf, loss);
+    else
+      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, false, false, STAGE, MSE>), dim3(brick_grid(g.nbricks)),
+                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, f, grad, y, inv_n, dldf, loss);
+  }
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
 template <class SP, class CT, class AT>
@@ -215,37 +252,14 @@ lsp_status launch_eval(const lsp_vol_s* v, const float* x, int64_t n, const void
                        hipStream_t st) {
   AT* fo = static_cast<AT*>(f);
   AT* go = static_cast<AT*>(grad);
-  if (!ws) {
-    if (grad)
-      hipLaunchKernelGGL((k_eval<SP, CT, AT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
-                         static_cast<long long>(n), nullptr, fo, go);
-    else
-      hipLaunchKernelGGL((k_eval<SP, CT, AT, false, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
-                         static_cast<long long>(n), nullptr, fo, go);
-    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
-  }
-  long long items;
-  bool split;
-  const unsigned* perm = sched_perm<SP>(v, n, ws, items, split);
-  if (split) {
-    hipLaunchKernelGGL((k_fill_zero<AT>), dim3(fill_grid(n)), dim3(256), 0, st, fo, static_cast<long long>(n));
-    if (grad) {
-      hipLaunchKernelGGL((k_fill_zero<AT>), dim3(fill_grid(n * SP::S)), dim3(256), 0, st, go,
-                         static_cast<long long>(n * SP::S));
-      hipLaunchKernelGGL((k_eval<SP, CT, AT, true, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
-                         items, perm, fo, go);
-    } else {
-      hipLaunchKernelGGL((k_eval<SP, CT, AT, false, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
-                         items, perm, fo, go);
-    }
-  } else {
-    if (grad)
-      hipLaunchKernelGGL((k_eval<SP, CT, AT, true, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
-                         items, perm, fo, go);
-    else
-      hipLaunchKernelGGL((k_eval<SP, CT, AT, false, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
-                         items, perm, fo, go);
-  }
+  if (ws)
+    return launch_binned_eval<SP, CT, AT, false>(v, x, n, ws, fo, go, nullptr, nullptr, nullptr, st);
+  if (grad)
+    hipLaunchKernelGGL((k_eval<SP, CT, AT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
+                       static_cast<long long>(n), nullptr, fo, go);
+  else
+    hipLaunchKernelGGL((k_eval<SP, CT, AT, false, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
+                       static_cast<long long>(n), nullptr, fo, go);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
@@ -265,19 +279,9 @@ template <class SP, class CT>
 lsp_status launch_mse(const lsp_vol_s* v, const float* x, const float* y, int64_t n, const void* ws, float* f,
                       float* dldf, double* loss, hipStream_t st) {
   const float inv_n = 1.0f / static_cast<float>(n);
-  long long items = n;
-  bool split = false;
-  const unsigned* perm = ws ? sched_perm<SP>(v, n, ws, items, split) : nullptr;
-  if (!split) {
-    hipLaunchKernelGGL((k_eval_mse<SP, CT>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x, y,
-                       static_cast<long long>(n), perm, inv_n, f, dldf, loss);
-  } else {
-    hipLaunchKernelGGL((k_fill_zero<float>), dim3(fill_grid(n)), dim3(256), 0, st, f, static_cast<long long>(n));
-    hipLaunchKernelGGL((k_eval<SP, CT, float, false, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, x,
-                       items, perm, f, static_cast<float*>(nullptr));
-    hipLaunchKernelGGL(k_mse_head, dim3(grid_of(n)), dim3(256), 0, st, f, y, static_cast<long long>(n), inv_n, dldf,
-                       loss);
-  }
+  if (ws) return launch_binned_eval<SP, CT, float, true>(v, x, n, ws, f, nullptr, y, dldf, loss, st);
+  hipLaunchKernelGGL((k_eval_mse<SP, CT>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x, y,
+                     static_cast<long long>(n), nullptr, inv_n, f, dldf, loss);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
@@ -297,27 +301,35 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
                       float* const* grad_c, float* grad_x, hipStream_t st) {
   GradVol gv{};
   for (int k = 0; k < SP::M; ++k) gv.base[k] = grad_c[k];
-  long long items = n;
-  bool split = false;
-  const unsigned* perm = ws ? sched_perm<SP>(v, n, ws, items, split) : nullptr;
-  if (split) {
-    if (grad_x) {
-      hipLaunchKernelGGL((k_fill_zero<float>), dim3(fill_grid(n * SP::S)), dim3(256), 0, st, grad_x,
-                         static_cast<long long>(n * SP::S));
-      hipLaunchKernelGGL((k_adjoint<SP, CT, true, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x, g,
-                         items, perm, grad_x);
-    } else {
-      hipLaunchKernelGGL((k_adjoint<SP, CT, false, true>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x,
-                         g, items, perm, grad_x);
-    }
-  } else {
+  if (!ws) {
     if (grad_x)
-      hipLaunchKernelGGL((k_adjoint<SP, CT, true, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x, g,
-                         items, perm, grad_x);
+      hipLaunchKernelGGL((k_adjoint<SP, CT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, gv, x, g,
+                         static_cast<long long>(n), nullptr, grad_x);
     else
-      hipLaunchKernelGGL((k_adjoint<SP, CT, false, false>), dim3(grid_of(items)), dim3(256), 0, st, v->vol, gv, x,
-                         g, items, perm, grad_x);
+      hipLaunchKernelGGL((k_adjoint<SP, CT, false, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, gv, x, g,
+                         static_cast<long long>(n), nullptr, grad_x);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
   }
+  const Bin bn = make_bin<SP>(v, n);
+  const BinGeom& gm = bn.g;
+  const char* base = static_cast<const char*>(ws);
+  const unsigned* start = reinterpret_cast<const unsigned*>(base + bn.off_start);
+  const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
+  constexpr bool SPLIT = SplitPolicy<SP>::value;
+  constexpr bool STAGE = SP::S == 3;
+  const size_t lds = grad_x ? bn.lds_adj : bn.lds_adj / 2;
+  if (lds > kLdsBudget) return LSP_ERR_UNSUPPORTED;
+  float* gx_out = grad_x;
+  if constexpr (SPLIT) gx_out = reinterpret_cast<float*>(const_cast<char*>(base) + bn.off_gpart);
+  if (grad_x)
+    hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, STAGE>), dim3(brick_grid(gm.nbricks)), dim3(256), lds,
+                       st, v->vol, gv, gm, recs, start, g, gx_out);
+  else
+    hipLaunchKernelGGL((k_adjoint_binned<SP, CT, false, SPLIT, STAGE>), dim3(brick_grid(gm.nbricks)), dim3(256),
+                       lds, st, v->vol, gv, gm, recs, start, g, gx_out);
+  if (SPLIT && grad_x)
+    hipLaunchKernelGGL((k_combine_gx<SP>), dim3(grid_of(n * SP::S)), dim3(256), 0, st, gx_out,
+                       static_cast<long long>(n), grad_x);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
@@ -334,7 +346,7 @@ lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t 
 
 template <class SP>
 lsp_status sched_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes) {
-  *bytes = make_sched<SP>(v, n).bytes;
+  *bytes = make_bin<SP>(v, n).bytes;
   return LSP_OK;
 }
 

@@ -1,0 +1,589 @@
+// Binned evaluation of random queries (gfx950).
+//
+// The fast scheme of Sec. 4 evaluates each query from a fixed stencil of
+// coefficients around its cell.  For queries in random order the stencils of
+// neighbouring lanes are unrelated and every gather misses the caches.  The
+// paper points out that combining the reads of one coset exploits data
+// locality (Sec. 4, memory layout); here the queries are binned by brick of
+// cells first, and one workgroup evaluates one brick:
+//
+//   1. k_bin_hist   per tile of items, an LDS histogram of item keys;
+//   2. k_bin_colscan + exclusive scan: the start of every key's run and of
+//      every (tile, key) sub-run in the key-sorted order;
+//   3. k_bin_place  per tile, LDS cursors place each item's record
+//      (query coordinates + item id) at its sorted position; a tile's items of
+//      one key land contiguously;
+//   4. k_eval_binned / k_adjoint_binned: one workgroup per brick stages the
+//      brick's coefficients (plus the stencil halo, zero outside the volume)
+//      into LDS with coalesced loads, then evaluates its queries from LDS.
+//      The adjoint accumulates the scatter-add into an LDS copy of the same
+//      region and flushes it with one global atomic per touched site.
+//
+// key = brick (linear, x fastest) * kpb + sub-region: for splines with several
+// sub-regions after the fold (K > 1) a work item is one (query, coset) pair,
+// and the items of one brick are grouped by sub-region, so a wave runs one
+// polynomial set instead of predicating all of them (Sec. 4.3).  Per-coset
+// results go to partial buffers and are summed by a combine kernel.
+
+namespace lsp {
+
+struct BinGeom {
+  int bshift;           // brick edge B = 1 << bshift cells per axis
+  int nb[kMaxDim];      // bricks per axis
+  unsigned nbricks;
+  int kpb;              // keys per brick: 1, or K for coset-split items
+  unsigned nkeys;       // nbricks * kpb
+  int tiles;            // histogram tiles
+  long long tile_items;
+  long long n;          // queries
+  long long items;      // work items (n, or n * M when split)
+};
+
+// Work items are (query, coset) pairs, grouped by sub-region, when the spline
+// has several sub-regions with costly polynomials; cheap ones are evaluated
+// per query with the sub-region branch left to diverge.
+template <class SP>
+struct SplitPolicy {
+  static constexpr int avg_nnz() {
+    int t = 0;
+    for (int k = 0; k < SP::K; ++k) t += SP::NNZ[k];
+    return t / SP::K;
+  }
+  static constexpr bool value = SP::K > 1 && avg_nnz() >= 200;
+};
+
+template <int S> struct Rec;
+template <> struct Rec<3> { float4 a; };             // x0 x1 x2 | item
+template <> struct Rec<4> { float4 a; uint4 b; };    // x0..x3 | item
+
+template <class SP> struct Staged {
+  // per coset the staged cells are [b B - 1 + OMIN, b B + B - 1 + OMAX] per axis
+  __host__ __device__ static constexpr int width(int B) { return B + 1 + SP::OMAX - SP::OMIN; }
+  __host__ __device__ static constexpr int volume(int B) {
+    int v = 1;
+    for (int d = 0; d < SP::S; ++d) v *= width(B);
+    return v;
+  }
+};
+
+template <class SP, bool SPLIT>
+__device__ __forceinline__ void split_item(long long t, long long& q, int& k) {
+  if constexpr (SPLIT) {
+    q = t / SP::M;
+    k = static_cast<int>(t - q * SP::M);
+  } else {
+    q = t;
+    k = 0;
+  }
+}
+
+// cell index of coset k for query x (as fold_query computes it)
+template <class SP>
+__device__ __forceinline__ int cell_of(const float* xq, int k, int d) {
+  float fl = floorf((xq[d] - static_cast<float>(coset_shift<SP>(k, d))) * (1.0f / SP::D));
+  fl = fl > 1e7f ? 1e7f : (fl < -1e7f ? -1e7f : fl);
+  return (fl == fl) ? static_cast<int>(fl) : 0;
+}
+
+template <class SP, bool SPLIT>
+__device__ __forceinline__ unsigned item_key(const Vol& vol, const BinGeom& g, const float* xq, int k) {
+  unsigned brick = 0, mul = 1;
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) {
+    int b = cell_of<SP>(xq, k, d) >> g.bshift;
+    b = b < 0 ? 0 : (b >= g.nb[d] ? g.nb[d] - 1 : b);
+    brick += static_cast<unsigned>(b) * mul;
+    mul *= static_cast<unsigned>(g.nb[d]);
+  }
+  unsigned key = brick * static_cast<unsigned>(g.kpb);
+  if constexpr (SPLIT) {
+    Folded<SP, float> F;
+    fold_query<SP, float>(xq, k, vol, F);
+    key += static_cast<unsigned>(SP::template orbit<float>(F.up));
+  }
+  return key;
+}
+
+template <class SP>
+__device__ __forceinline__ void load_x(const float* __restrict__ x, long long q, float* xq) {
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
+}
+
+// 1. per-tile histogram of keys (dynamic LDS: nkeys counters)
+template <class SP, bool SPLIT>
+__global__ void __launch_bounds__(1024) k_bin_hist(Vol vol, BinGeom g, const float* __restrict__ x,
+                                                   unsigned* __restrict__ hist) {
+  extern __shared__ unsigned cnt[];
+  for (unsigned i = threadIdx.x; i < g.nkeys; i += blockDim.x) cnt[i] = 0u;
+  __syncthreads();
+  const long long t0 = static_cast<long long>(blockIdx.x) * g.tile_items;
+  const long long t1 = t0 + g.tile_items < g.items ? t0 + g.tile_items : g.items;
+  for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+    long long q;
+    int k;
+    split_item<SP, SPLIT>(t, q, k);
+    float xq[SP::S];
+    load_x<SP>(x, q, xq);
+    atomicAdd(cnt + item_key<SP, SPLIT>(vol, g, xq, k), 1u);
+  }
+  __syncthreads();
+  unsigned* out = hist + static_cast<size_t>(blockIdx.x) * g.nkeys;
+  for (unsigned i = threadIdx.x; i < g.nkeys; i += blockDim.x) out[i] = cnt[i];
+}
+
+// 2. per key: exclusive running sum over tiles (in place) and the key total
+__global__ void __launch_bounds__(256) k_bin_colscan(unsigned* __restrict__ hist, int tiles, unsigned nkeys,
+                                                     unsigned* __restrict__ tot) {
+  const unsigned key = blockIdx.x * blockDim.x + threadIdx.x;
+  if (key > nkeys) return;
+  if (key == nkeys) {
+    tot[key] = 0u;
+    return;
+  }
+  unsigned run = 0u;
+  int t = 0;
+  for (; t + 16 <= tiles; t += 16) {
+    unsigned h[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) h[j] = hist[static_cast<size_t>(t + j) * nkeys + key];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      hist[static_cast<size_t>(t + j) * nkeys + key] = run;
+      run += h[j];
+    }
+  }
+  for (; t < tiles; ++t) {
+    unsigned* p = hist + static_cast<size_t>(t) * nkeys + key;
+    const unsigned h = *p;
+    *p = run;
+    run += h;
+  }
+  tot[key] = run;
+}
+
+// 3. place each item's record at its sorted position
+template <class SP, bool SPLIT>
+__global__ void __launch_bounds__(1024) k_bin_place(Vol vol, BinGeom g, const float* __restrict__ x,
+                                                    const unsigned* __restrict__ hist,
+                                                    const unsigned* __restrict__ start, Rec<SP::S>* __restrict__ recs) {
+  extern __shared__ unsigned cur[];
+  const unsigned* h = hist + static_cast<size_t>(blockIdx.x) * g.nkeys;
+  for (unsigned i = threadIdx.x; i < g.nkeys; i += blockDim.x) cur[i] = h[i] + start[i];
+  __syncthreads();
+  const long long t0 = static_cast<long long>(blockIdx.x) * g.tile_items;
+  const long long t1 = t0 + g.tile_items < g.items ? t0 + g.tile_items : g.items;
+  for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+    long long q;
+    int k;
+    split_item<SP, SPLIT>(t, q, k);
+    float xq[SP::S];
+    load_x<SP>(x, q, xq);
+    const unsigned pos = atomicAdd(cur + item_key<SP, SPLIT>(vol, g, xq, k), 1u);
+    Rec<SP::S> r;
+    if constexpr (SP::S == 3) {
+      r.a = make_float4(xq[0], xq[1], xq[2], __uint_as_float(static_cast<unsigned>(t)));
+    } else {
+      r.a = make_float4(xq[0], xq[1], xq[2], xq[3]);
+      r.b = make_uint4(static_cast<unsigned>(t), 0u, 0u, 0u);
+    }
+    recs[pos] = r;
+  }
+}
+
+template <class SP>
+__device__ __forceinline__ unsigned rec_item(const Rec<SP::S>& r, float* xq) {
+  if constexpr (SP::S == 3) {
+    xq[0] = r.a.x; xq[1] = r.a.y; xq[2] = r.a.z;
+    return __float_as_uint(r.a.w);
+  } else {
+    xq[0] = r.a.x; xq[1] = r.a.y; xq[2] = r.a.z; xq[3] = r.a.w;
+    return r.b.x;
+  }
+}
+
+// brick handled by this workgroup: each XCD (blocks are dealt round-robin to
+// the 8 XCDs) takes a contiguous run of bricks, so neighbouring bricks share
+// their halo in one L2
+__device__ __forceinline__ long long brick_of_block(unsigned nbricks) {
+  const unsigned per = (nbricks + 7u) / 8u;
+  const unsigned xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
+  if (slot >= per) return -1;
+  const unsigned b = xcd * per + slot;
+  return b < nbricks ? static_cast<long long>(b) : -1;
+}
+
+// staged coefficient region of one brick
+template <class SP, class AT>
+struct StageInfo {
+  int org[SP::S];     // global cell index of the region origin per axis
+  int W;              // region width
+  int vol;            // W^S
+  int ls[SP::S];      // LDS strides
+};
+
+template <class SP, class AT>
+__device__ __forceinline__ void stage_info(const BinGeom& g, long long brick, StageInfo<SP, AT>& si) {
+  const int B = 1 << g.bshift;
+  si.W = Staged<SP>::width(B);
+  long long rem = brick;
+  int st = 1;
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) {
+    const int b = static_cast<int>(rem % g.nb[d]);
+    rem /= g.nb[d];
+    si.org[d] = b * B - 1 + SP::OMIN;
+    si.ls[d] = st;
+    st *= si.W;
+  }
+  si.vol = st;
+}
+
+template <class SP, class CT, class AT>
+__device__ __forceinline__ void stage_load(const Vol& vol, const StageInfo<SP, AT>& si, AT* lds) {
+  const int total = SP::M * si.vol;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int k = e / si.vol;
+    int r = e - k * si.vol;
+    long long off = 0;
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) {
+      const int c = si.org[d] + r % si.W;
+      r /= si.W;
+      in = in && c >= 0 && c < vol.dims[d];
+      off += static_cast<long long>(c) * vol.stride[d];
+    }
+    const CT* base = static_cast<const CT*>(pick<SP::M>(vol.base, k));
+    lds[e] = in ? load_coef<CT, AT>(base + off) : AT(0);
+  }
+}
+
+// LDS stride W^a of original axis a (a varies per lane: computed values only)
+template <class SP, class AT>
+__device__ __forceinline__ int lds_stride(const StageInfo<SP, AT>& si, int a) {
+  const int W = si.W, W2 = W * W;
+  int v = (a == 1) ? W : 1;
+  v = (a == 2) ? W2 : v;
+  if constexpr (SP::S == 4) v = (a == 3) ? W2 * W : v;
+  return v;
+}
+
+// item's stencil inside the staged region?
+template <class SP, class AT>
+__device__ __forceinline__ bool stageable(const StageInfo<SP, AT>& si, const Folded<SP, AT>& F) {
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) {
+    const int li = F.i[d] - si.org[d];
+    ok = ok && (li + SP::OMIN >= 0) && (li + SP::OMAX < si.W);
+  }
+  return ok;
+}
+
+// gather / scatter through the fold inside an LDS region
+template <class SP, class AT>
+struct GatherLds {
+  const AT* origin;
+  int st[SP::S];
+  __device__ __forceinline__ void init(const AT* region, const StageInfo<SP, AT>& si, const Folded<SP, AT>& F) {
+    int off = 0;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) off += (F.i[d] - si.org[d]) * si.ls[d];
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const int s = lds_stride<SP, AT>(si, F.ax[r]);
+      st[r] = F.sg[r] > 0 ? s : -s;
+      if (F.sg[r] < 0) off += s;
+    }
+    origin = region + off;
+  }
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ AT c() const {
+    constexpr int J[4] = {J0, J1, J2, J3};
+    int off = 0;
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) off += J[r] * st[r];
+    return origin[off];
+  }
+};
+
+template <class SP>
+struct ScatterLds {
+  float* origin;
+  int st[SP::S];
+  float g;
+  __device__ __forceinline__ void init(float* region, const StageInfo<SP, float>& si, const Folded<SP, float>& F,
+                                       float gq) {
+    int off = 0;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) off += (F.i[d] - si.org[d]) * si.ls[d];
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const int s = lds_stride<SP, float>(si, F.ax[r]);
+      st[r] = F.sg[r] > 0 ? s : -s;
+      if (F.sg[r] < 0) off += s;
+    }
+    origin = region + off;
+    g = gq;
+  }
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ void put(float w) {
+    constexpr int J[4] = {J0, J1, J2, J3};
+    int off = 0;
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) off += J[r] * st[r];
+    atomicAdd(origin + off, g * w);
+  }
+};
+
+// one coset's psi (and folded gradient mapped back to x) from LDS or global
+template <class SP, class CT, class AT, bool GRAD, bool STAGE>
+__device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP, AT>& si, const AT* lds, int k,
+                                             const AT* xq, AT& f, AT* gx) {
+  Folded<SP, AT> F;
+  fold_query<SP, AT>(xq, k, vol, F);
+  const int ob = SP::template orbit<AT>(F.up);
+  AT b[SP::NMON];
+  bool staged = false;
+  if constexpr (STAGE) staged = stageable<SP, AT>(si, F);
+  if (staged) {
+    GatherLds<SP, AT> g;
+    g.init(lds + k * si.vol, si, F);
+    SP::template b_any<AT>(ob, g, b);
+  } else if (F.interior) {
+    Gather<SP, CT, AT, false> g;
+    g.init(vol, k, F);
+    SP::template b_any<AT>(ob, g, b);
+  } else {
+    Gather<SP, CT, AT, true> g;
+    g.init(vol, k, F);
+    SP::template b_any<AT>(ob, g, b);
+  }
+  AT mono[SP::NMON];
+  monomials<SP, AT>(F.up, mono);
+  AT dpsi[SP::S];
+  f += poly_eval<SP, AT, GRAD>(b, mono, dpsi);
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const AT v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : AT(0);
+    }
+  }
+}
+
+// 4a. forward, one workgroup per brick.
+//   not SPLIT: f[q] (and grad[q]) directly; MSE also writes dL/df and adds the loss.
+//   SPLIT:     fpart[k * n + q] (and gpart) for the combine kernel.
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE>
+__global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
+                                                     const unsigned* __restrict__ start, AT* __restrict__ f,
+                                                     AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
+                                                     float* __restrict__ dldf, double* __restrict__ loss) {
+  extern __shared__ unsigned char smem[];
+  AT* lds = reinterpret_cast<AT*>(smem);
+  const long long brick = brick_of_block(g.nbricks);
+  if (brick < 0) return;
+  const unsigned k0 = static_cast<unsigned>(brick) * g.kpb;
+  const unsigned lo = start[k0], hi = start[k0 + g.kpb];
+  if (lo == hi) return;
+  StageInfo<SP, AT> si;
+  stage_info<SP, AT>(g, brick, si);
+  if constexpr (STAGE) {
+    stage_load<SP, CT, AT>(vol, si, lds);
+    __syncthreads();
+  }
+  float r2 = 0.f;
+  for (unsigned t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    float xf[SP::S];
+    const unsigned item = rec_item<SP>(recs[t], xf);
+    long long q;
+    int k;
+    split_item<SP, SPLIT>(item, q, k);
+    AT xq[SP::S];
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) xq[d] = static_cast<AT>(xf[d]);
+    AT acc = AT(0);
+    AT gx[SP::S];
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) gx[d] = AT(0);
+    if constexpr (SPLIT) {
+      coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds, k, xq, acc, gx);
+      const long long slot = static_cast<long long>(k) * g.n + q;
+      f[slot] = acc;
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) grad[slot * SP::S + d] = gx[d];
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < SP::M; ++kk) coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds, kk, xq, acc, gx);
+      f[q] = acc;
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = gx[d];
+      }
+      if constexpr (MSE) {
+        const float r = static_cast<float>(acc) - y[q];
+        dldf[q] = 2.f * r * inv_n;
+        r2 += r * r;
+      }
+    }
+  }
+  if constexpr (MSE && !SPLIT) mse_reduce(r2, static_cast<double>(inv_n), loss);
+}
+
+// 4b. combine per-coset partials: f = sum_k fpart[k], grad likewise; optional MSE head
+template <class SP, class AT, bool GRAD, bool MSE>
+__global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, const AT* __restrict__ gpart,
+                                                 long long n, AT* __restrict__ f, AT* __restrict__ grad,
+                                                 const float* __restrict__ y, float inv_n, float* __restrict__ dldf,
+                                                 double* __restrict__ loss) {
+  float r2 = 0.f;
+  for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
+       q += static_cast<long long>(gridDim.x) * blockDim.x) {
+    AT acc = AT(0);
+#pragma unroll
+    for (int k = 0; k < SP::M; ++k) acc += fpart[k * n + q];
+    f[q] = acc;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) {
+        AT s = AT(0);
+#pragma unroll
+        for (int k = 0; k < SP::M; ++k) s += gpart[(k * n + q) * SP::S + d];
+        grad[q * SP::S + d] = s;
+      }
+    }
+    if constexpr (MSE) {
+      const float r = static_cast<float>(acc) - y[q];
+      dldf[q] = 2.f * r * inv_n;
+      r2 += r * r;
+    }
+  }
+  if constexpr (MSE) mse_reduce(r2, static_cast<double>(inv_n), loss);
+}
+
+// 5. adjoint, one workgroup per brick: scatter-add g * w into an LDS copy of
+// the brick's region, flush touched sites with one global atomic each.
+//   not SPLIT: grad_x[q] = g_q * grad f directly; SPLIT: gpart[k * n + q].
+template <class SP, class CT, bool GRADX, bool SPLIT, bool STAGE>
+__global__ void __launch_bounds__(256) k_adjoint_binned(Vol vol, GradVol gvol, BinGeom g,
+                                                        const Rec<SP::S>* __restrict__ recs,
+                                                        const unsigned* __restrict__ start,
+                                                        const float* __restrict__ gout, float* __restrict__ grad_x) {
+  extern __shared__ unsigned char smem[];
+  const long long brick = brick_of_block(g.nbricks);
+  if (brick < 0) return;
+  const unsigned k0 = static_cast<unsigned>(brick) * g.kpb;
+  const unsigned lo = start[k0], hi = start[k0 + g.kpb];
+  if (lo == hi) return;
+  StageInfo<SP, float> si;
+  stage_info<SP, float>(g, brick, si);
+  float* lds_g = reinterpret_cast<float*>(smem);                 // gradient region (M * vol)
+  float* lds_c = lds_g + (STAGE ? SP::M * si.vol : 0);            // coefficient region (GRADX)
+  if constexpr (STAGE) {
+    for (int e = threadIdx.x; e < SP::M * si.vol; e += blockDim.x) lds_g[e] = 0.f;
+    if constexpr (GRADX) stage_load<SP, CT, float>(vol, si, lds_c);
+    __syncthreads();
+  }
+  for (unsigned t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    float xq[SP::S];
+    const unsigned item = rec_item<SP>(recs[t], xq);
+    long long q;
+    int k;
+    split_item<SP, SPLIT>(item, q, k);
+    const float gq = gout[q];
+    float gx[SP::S];
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < (SPLIT ? 1 : SP::M); ++kk) {
+      const int kc = SPLIT ? k : kk;
+      Folded<SP, float> F;
+      fold_query<SP, float>(xq, kc, vol, F);
+      const int ob = SP::template orbit<float>(F.up);
+      float mono[SP::NMON];
+      monomials<SP, float>(F.up, mono);
+      bool staged = false;
+      if constexpr (STAGE) staged = stageable<SP, float>(si, F);
+      if (staged) {
+        ScatterLds<SP> sc;
+        sc.init(lds_g + kc * si.vol, si, F, gq);
+        SP::template w_any<float>(ob, sc, mono);
+      } else if (F.interior) {
+        Scatter<SP, false> sc;
+        sc.init(vol, pick<SP::M>(gvol.base, kc), F, gq);
+        SP::template w_any<float>(ob, sc, mono);
+      } else {
+        Scatter<SP, true> sc;
+        sc.init(vol, pick<SP::M>(gvol.base, kc), F, gq);
+        SP::template w_any<float>(ob, sc, mono);
+      }
+      if constexpr (GRADX) {
+        float b[SP::NMON];
+        if (staged) {
+          GatherLds<SP, float> gg;
+          gg.init(lds_c + kc * si.vol, si, F);
+          SP::template b_any<float>(ob, gg, b);
+        } else if (F.interior) {
+          Gather<SP, CT, float, false> gg;
+          gg.init(vol, kc, F);
+          SP::template b_any<float>(ob, gg, b);
+        } else {
+          Gather<SP, CT, float, true> gg;
+          gg.init(vol, kc, F);
+          SP::template b_any<float>(ob, gg, b);
+        }
+        float dpsi[SP::S];
+        (void)poly_eval<SP, float, true>(b, mono, dpsi);
+#pragma unroll
+        for (int r = 0; r < SP::S; ++r) {
+          const float v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
+#pragma unroll
+          for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : 0.f;
+        }
+      }
+    }
+    if constexpr (GRADX) {
+      const long long slot = SPLIT ? static_cast<long long>(k) * g.n + q : q;
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = gq * gx[d];
+    }
+  }
+  if constexpr (STAGE) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < SP::M * si.vol; e += blockDim.x) {
+      const float v = lds_g[e];
+      if (v == 0.f) continue;
+      const int k = e / si.vol;
+      int r = e - k * si.vol;
+      long long off = 0;
+      bool in = true;
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) {
+        const int c = si.org[d] + r % si.W;
+        r /= si.W;
+        in = in && c >= 0 && c < vol.dims[d];
+        off += static_cast<long long>(c) * vol.stride[d];
+      }
+      if (in) atomicAdd(pick<SP::M>(gvol.base, k) + off, v);
+    }
+  }
+}
+
+// sum the per-coset grad_x partials of a split adjoint
+template <class SP>
+__global__ void __launch_bounds__(256) k_combine_gx(const float* __restrict__ gpart, long long n,
+                                                    float* __restrict__ grad_x) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n * SP::S) return;
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < SP::M; ++k) s += gpart[k * n * SP::S + i];
+  grad_x[i] = s;
+}
+
+}  // namespace lsp

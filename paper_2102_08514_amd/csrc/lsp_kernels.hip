@@ -88,12 +88,49 @@ struct Folded {
   AT up[SP::S];       // folded offset from the cell centre, in the chamber
   int ax[SP::S];      // folded axis r comes from original axis ax[r]
   int sg[SP::S];      // and carries sign sg[r]: up[r] = sg[r] * u[ax[r]]
+  int pi[SP::S];      // cell index along original axis ax[r]
   bool interior;      // the whole stencil lies inside the stored arrays
 };
 
 template <class AT> __device__ __forceinline__ AT afloor(AT v);
 template <> __device__ __forceinline__ float afloor<float>(float v) { return floorf(v); }
 template <> __device__ __forceinline__ double afloor<double>(double v) { return floor(v); }
+
+// compare-exchange of the sorting network (positions are compile-time)
+template <int P, int Q, class AT>
+__device__ __forceinline__ void cswap(AT* v, int* ax, int* sg, int* pi) {
+  const bool sw = v[P] < v[Q];
+  const AT tv = sw ? v[Q] : v[P], uv = sw ? v[P] : v[Q];
+  v[P] = tv; v[Q] = uv;
+  const int ta = sw ? ax[Q] : ax[P], ua = sw ? ax[P] : ax[Q];
+  ax[P] = ta; ax[Q] = ua;
+  const int ts = sw ? sg[Q] : sg[P], us = sw ? sg[P] : sg[Q];
+  sg[P] = ts; sg[Q] = us;
+  const int tp = sw ? pi[Q] : pi[P], up = sw ? pi[P] : pi[Q];
+  pi[P] = tp; pi[Q] = up;
+}
+
+// extent and element stride of original axis a (a varies per lane): selects
+// between computed values, never an indexed array (which would live in
+// scratch memory)
+template <int S>
+__device__ __forceinline__ int axis_stride(const int* dims, int a) {
+  const int n0 = dims[0];
+  const int n01 = n0 * dims[1];
+  int s = (a == 1) ? n0 : 1;
+  s = (a == 2) ? n01 : s;
+  if constexpr (S == 4) s = (a == 3) ? n01 * dims[2] : s;
+  return s;
+}
+
+template <int S>
+__device__ __forceinline__ int axis_dim(const int* dims, int a) {
+  const int n0 = dims[0], n1 = dims[1], n2 = dims[2];
+  int n = (a == 1) ? n1 : n0;
+  n = (a == 2) ? n2 : n;
+  if constexpr (S == 4) n = (a == 3) ? dims[3] : n;
+  return n;
+}
 
 template <class SP, class AT>
 __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, Folded<SP, AT>& F) {
@@ -109,6 +146,7 @@ __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, F
     int id = (fl == fl) ? static_cast<int>(fl) : 0;   // NaN queries: any in-range cell
     AT u = (xp - AT(SP::D) * fl) - AT(0.5 * SP::D);
     F.i[d] = id;
+    F.pi[d] = id;
     interior = interior && (id + SP::OMIN >= 0) && (id + SP::OMAX < vol.dims[d]);
     a[d] = u;
     F.ax[d] = d;
@@ -119,16 +157,11 @@ __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, F
 #pragma unroll
   for (int d = 0; d < S; ++d) v[d] = a[d] < AT(0) ? -a[d] : a[d];
   // sorting network, descending on |u|, carrying axis and sign
-  auto cswap = [&](int p, int q) {
-    bool sw = v[p] < v[q];
-    AT tv = sw ? v[q] : v[p]; AT uv = sw ? v[p] : v[q]; v[p] = tv; v[q] = uv;
-    int ta = sw ? F.ax[q] : F.ax[p]; int ua = sw ? F.ax[p] : F.ax[q]; F.ax[p] = ta; F.ax[q] = ua;
-    int ts = sw ? F.sg[q] : F.sg[p]; int us = sw ? F.sg[p] : F.sg[q]; F.sg[p] = ts; F.sg[q] = us;
-  };
   if constexpr (S == 3) {
-    cswap(0, 1); cswap(1, 2); cswap(0, 1);
+    cswap<0, 1>(v, F.ax, F.sg, F.pi); cswap<1, 2>(v, F.ax, F.sg, F.pi); cswap<0, 1>(v, F.ax, F.sg, F.pi);
   } else {
-    cswap(0, 1); cswap(2, 3); cswap(0, 2); cswap(1, 3); cswap(1, 2);
+    cswap<0, 1>(v, F.ax, F.sg, F.pi); cswap<2, 3>(v, F.ax, F.sg, F.pi); cswap<0, 2>(v, F.ax, F.sg, F.pi);
+    cswap<1, 3>(v, F.ax, F.sg, F.pi); cswap<1, 2>(v, F.ax, F.sg, F.pi);
   }
   if constexpr (SP::FOLD_D) {
     // even sign changes only: an odd number of negative components leaves the
@@ -160,11 +193,11 @@ struct Gather {
 #pragma unroll
     for (int r = 0; r < SP::S; ++r) {
       const int a = F.ax[r];
-      const int s = vol.stride[a];
+      const int s = axis_stride<SP::S>(vol.dims, a);
       st[r] = F.sg[r] > 0 ? s : -s;
       if (F.sg[r] < 0) off += s;
       if constexpr (CHECK) {
-        const int ia = F.i[a], n = vol.dims[a];
+        const int ia = F.pi[r], n = axis_dim<SP::S>(vol.dims, a);
         // sg > 0: 0 <= ia + J < n ; sg < 0: 0 <= ia + 1 - J < n
         jlo[r] = F.sg[r] > 0 ? -ia : ia + 2 - n;
         jhi[r] = F.sg[r] > 0 ? n - 1 - ia : ia + 1;
@@ -207,11 +240,11 @@ struct Scatter {
 #pragma unroll
     for (int r = 0; r < SP::S; ++r) {
       const int a = F.ax[r];
-      const int s = vol.stride[a];
+      const int s = axis_stride<SP::S>(vol.dims, a);
       st[r] = F.sg[r] > 0 ? s : -s;
       if (F.sg[r] < 0) off += s;
       if constexpr (CHECK) {
-        const int ia = F.i[a], n = vol.dims[a];
+        const int ia = F.pi[r], n = axis_dim<SP::S>(vol.dims, a);
         jlo[r] = F.sg[r] > 0 ? -ia : ia + 2 - n;
         jhi[r] = F.sg[r] > 0 ? n - 1 - ia : ia + 1;
       }
@@ -392,20 +425,28 @@ __global__ void __launch_bounds__(256) k_eval(Vol vol, const float* __restrict__
 
 // mean-squared-error head on a complete f: dL/df = 2 (f - y) / N, L += sum (f - y)^2 / N
 __device__ __forceinline__ void mse_reduce(float r2, double inv_n, double* loss) {
+  // every thread of the block calls this: wave sums, then one atomic per block
+  __shared__ float wave_sum[16];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 64);
-  if ((threadIdx.x & 63) == 0) atomicAdd(loss, static_cast<double>(r2) * inv_n);
+  if ((threadIdx.x & 63) == 0) wave_sum[threadIdx.x >> 6] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (unsigned w = 0; w < (blockDim.x + 63) / 64; ++w) tot += static_cast<double>(wave_sum[w]);
+    atomicAdd(loss, tot * inv_n);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_mse_head(const float* __restrict__ f, const float* __restrict__ y,
                                                   long long n, float inv_n, float* __restrict__ dldf,
                                                   double* __restrict__ loss) {
-  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   float r2 = 0.f;
-  if (q < n) {
+  for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
+       q += static_cast<long long>(gridDim.x) * blockDim.x) {
     const float r = f[q] - y[q];
     dldf[q] = 2.f * r * inv_n;
-    r2 = r * r;
+    r2 += r * r;
   }
   mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
@@ -472,59 +513,7 @@ __global__ void __launch_bounds__(256) k_adjoint(Vol vol, GradVol gvol, const fl
 }
 
 // ----------------------------------------------------------------------------
-// Query schedule: a counting sort of the work items by key
-//   key = (sub-region, Morton index of the item's brick of cells)
-// (sub-region only for SPLIT items).  Items of one brick then run in the same
-// waves, so their stencils overlap in the L1/L2 caches, and SPLIT waves hold a
-// single sub-region, so the sub-region branch does not diverge.
-struct SchedGeom {
-  int bshift;           // brick = cell >> bshift per axis
-  int nbits;            // Morton bits per axis
-  int nb[kMaxDim];      // bricks per axis
-};
-
-template <class SP>
-__device__ __forceinline__ unsigned morton_key(const int* b, int nbits) {
-  unsigned code = 0;
-  for (int bit = 0; bit < nbits; ++bit) {
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) code |= static_cast<unsigned>((b[d] >> bit) & 1) << (bit * SP::S + d);
-  }
-  return code;
-}
-
-template <class SP, bool SPLIT>
-__global__ void __launch_bounds__(256) k_sched_keys(Vol vol, SchedGeom g, const float* __restrict__ x,
-                                                    long long n_items, unsigned* __restrict__ count,
-                                                    unsigned* __restrict__ key, unsigned* __restrict__ rank) {
-  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n_items) return;
-  long long q;
-  int k;
-  item_of<SP, SPLIT>(t, nullptr, q, k);
-  float xq[SP::S];
-#pragma unroll
-  for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
-  int b[SP::S];
-#pragma unroll
-  for (int d = 0; d < SP::S; ++d) {
-    float fl = floorf((xq[d] - static_cast<float>(coset_shift<SP>(k, d))) * (1.0f / SP::D));
-    fl = fl > 1e7f ? 1e7f : (fl < -1e7f ? -1e7f : fl);
-    const int i = (fl == fl) ? static_cast<int>(fl) : 0;
-    int bb = i >> g.bshift;
-    bb = bb < 0 ? 0 : (bb >= g.nb[d] ? g.nb[d] - 1 : bb);
-    b[d] = bb;
-  }
-  unsigned kk = morton_key<SP>(b, g.nbits);
-  if constexpr (SPLIT) {
-    Folded<SP, float> F;
-    fold_query<SP, float>(xq, k, vol, F);
-    kk += static_cast<unsigned>(SP::template orbit<float>(F.up)) << (g.nbits * SP::S);
-  }
-  key[t] = kk;
-  rank[t] = atomicAdd(count + kk, 1u);
-}
-
+// small utility kernels
 __global__ void __launch_bounds__(256) k_fill_u32(unsigned* __restrict__ p, long long n, unsigned v) {
   for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<long long>(gridDim.x) * blockDim.x)
@@ -599,15 +588,6 @@ __global__ void __launch_bounds__(256) k_scan_add(unsigned* __restrict__ out, co
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     if (base + j < n) out[base + j] += add;
-}
-
-__global__ void __launch_bounds__(256) k_sched_scatter(long long n_items, const unsigned* __restrict__ key,
-                                                       const unsigned* __restrict__ rank,
-                                                       const unsigned* __restrict__ offset,
-                                                       unsigned* __restrict__ perm) {
-  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n_items) return;
-  perm[offset[key[t]] + rank[t]] = static_cast<unsigned>(t);
 }
 
 // Ray-marched samples (orthographic): sample (ray r, step j) is at
