@@ -361,7 +361,7 @@ __device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP,
     SP::template b_any<AT>(ob, g, b);
   }
   AT mono[SP::NMON];
-  monomials<SP, AT>(F.up, mono);
+  monomials<SP, AT>(F.up, ob, mono);
   AT dpsi[SP::S];
   f += poly_eval<SP, AT, GRAD>(b, mono, dpsi);
   if constexpr (GRAD) {
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(256) k_adjoint_binned(Vol vol, GradVol gvol, B
       fold_query<SP, float>(xq, kc, vol, F);
       const int ob = SP::template orbit<float>(F.up);
       float mono[SP::NMON];
-      monomials<SP, float>(F.up, mono);
+      monomials<SP, float>(F.up, ob, mono);
       bool staged = false;
       if constexpr (STAGE) staged = stageable<SP, float>(si, F);
       if (staged) {

@@ -270,11 +270,16 @@ struct Scatter {
   }
 };
 
+// monomials of the folded point about the sub-region's origin (a chamber
+// vertex chosen by the generator for the sparsest polynomials)
 template <class SP, class AT>
-__device__ __forceinline__ void monomials(const AT* up, AT* mono) {
+__device__ __forceinline__ void monomials(const AT* up, int ob, AT* mono) {
+  AT z[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) z[d] = up[d] - SP::template origin<AT>(ob, d);
   mono[0] = AT(1);
 #pragma unroll
-  for (int m = 1; m < SP::NMON; ++m) mono[m] = mono[SP::MPARENT[m]] * up[SP::MVAR[m]];
+  for (int m = 1; m < SP::NMON; ++m) mono[m] = mono[SP::MPARENT[m]] * z[SP::MVAR[m]];
 }
 
 // psi and, optionally, its gradient in the folded frame from b and the monomials
@@ -314,7 +319,7 @@ __device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* x
     SP::template b_any<AT>(ob, g, b);
   }
   AT mono[SP::NMON];
-  monomials<SP, AT>(F.up, mono);
+  monomials<SP, AT>(F.up, ob, mono);
   AT dpsi[SP::S];
   f += poly_eval<SP, AT, GRAD>(b, mono, dpsi);
   if constexpr (GRAD) {
@@ -337,7 +342,7 @@ __device__ __forceinline__ void coset_adjoint(const Vol& vol, const GradVol& gvo
   fold_query<SP, float>(xq, k, vol, F);
   const int ob = SP::template orbit<float>(F.up);
   float mono[SP::NMON];
-  monomials<SP, float>(F.up, mono);
+  monomials<SP, float>(F.up, ob, mono);
   float* gbase = pick<SP::M>(gvol.base, k);
   if (F.interior) {
     Scatter<SP, false> sc;
