@@ -1,0 +1,141 @@
+"""The emitted HIP straight-line code, executed on the CPU, equals the exact
+tables: the b-form (monomial coefficients from the gathered coefficients,
+with factored pair sums) and the w-form (per-site weights) of every
+sub-region, about the sub-region's origin, and the sub-region selection.
+This pins the code generator's text, not only its data."""
+
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2102_08514_amd.gen.interp import orbit_of
+from paper_2102_08514_amd.gen.tables import GENERATED, load
+
+NAMES = ["bcc_linear", "cc_zp", "bcc_quartic", "fcc_6dir", "d4s_8dir"]
+
+
+def _functions(text):
+    """{name: body lines} for the b_k / w_k / origin device functions."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"static (?:void|AT|int) (b_\d+|w_\d+|origin|orbit)\(", line)
+        if m:
+            cur = m.group(1)
+            out[cur] = []
+            continue
+        if cur is not None:
+            if line.startswith("  }"):
+                cur = None
+            else:
+                out[cur].append(line.strip())
+    return out
+
+
+def _lit(s):
+    return float(s)
+
+
+def run_b(lines, c):
+    env = {f"x{r}": v for r, v in enumerate(c)}
+    b = {}
+    for ln in lines:
+        if ln.startswith("const AT x") and "g.template" in ln:
+            continue
+        m = re.match(r"const AT (x\d+) = fma\((x\d+), AT\(([^)]+)\), (x\d+)\);", ln)
+        if m:
+            env[m.group(1)] = env[m.group(2)] * _lit(m.group(3)) + env[m.group(4)]
+            continue
+        m = re.match(r"b\[(\d+)\] = (x\d+) \* AT\(([^)]+)\);", ln)
+        if m:
+            b[int(m.group(1))] = env[m.group(2)] * _lit(m.group(3))
+            continue
+        m = re.match(r"b\[(\d+)\] = fma\((x\d+), AT\(([^)]+)\), b\[\d+\]\);", ln)
+        if m:
+            b[int(m.group(1))] += env[m.group(2)] * _lit(m.group(3))
+            continue
+        m = re.match(r"b\[(\d+)\] = AT\(0\);", ln)
+        if m:
+            b[int(m.group(1))] = 0.0
+            continue
+        raise AssertionError(f"unparsed line: {ln}")
+    return b
+
+
+def run_w(lines, mono):
+    env = {}
+    sym = lambda s: mono[int(s[5:-1])] if s.startswith("mono[") else env[s]  # noqa: E731
+    w, cur = [], None
+    for ln in lines:
+        m = re.match(r"const AT (y\d+) = fma\((\S+), AT\(([^)]+)\), (\S+)\);", ln)
+        if m:
+            env[m.group(1)] = sym(m.group(2)) * _lit(m.group(3)) + sym(m.group(4))
+            continue
+        m = re.match(r"\{ AT wv = (\S+) \* AT\(([^)]+)\);", ln)
+        if m:
+            cur = sym(m.group(1)) * _lit(m.group(2))
+            continue
+        m = re.match(r"wv = fma\((\S+), AT\(([^)]+)\), wv\);", ln)
+        if m:
+            cur += sym(m.group(1)) * _lit(m.group(2))
+            continue
+        m = re.match(r"g\.template put<([-\d, ]+)>\(wv\); \}", ln)
+        if m:
+            w.append((tuple(int(v) for v in m.group(1).split(",")), cur))
+            continue
+        raise AssertionError(f"unparsed line: {ln}")
+    return w
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_emitted_code_matches_tables(name):
+    t = load(name)
+    text = open(f"{GENERATED}/{name}.inc").read()
+    fn = _functions(text)
+    mons = t.monomials()
+    rng = np.random.default_rng(5)
+    # origins per sub-region, from the emitted origin() selector
+    orig_lines = fn["origin"]
+    for k, orb in enumerate(t.orbits):
+        origin = []
+        for d in range(t.s):
+            line = next(ln for ln in orig_lines if ln.startswith(f"if (d == {d})"))
+            vals = [float(v) for v in re.findall(r"AT\(([-0-9.e]+)\)", line)]
+            # nested selector: value for ob == k is the k-th literal (last one is the default)
+            origin.append(vals[k] if k < len(vals) else vals[-1])
+        stencil = orb["stencil"]
+        # random gathered values and a random point: psi two ways
+        c = rng.uniform(-1, 1, len(stencil))
+        u = rng.uniform(0, t.D / 2, t.s)
+        z = u - np.array(origin)
+        b = run_b(fn[f"b_{k}"], c)
+        psi_code = sum(b.get(m, 0.0) * np.prod(z ** np.array(e)) for m, e in enumerate(mons))
+        psi_tab = sum(ci * float(P(tuple(Fraction(float(v)) for v in u))) for ci, P in zip(c, orb["polys"]))
+        assert abs(psi_code - psi_tab) < 1e-12, (k, psi_code, psi_tab)
+        mono = [float(np.prod(z ** np.array(e))) for e in mons]
+        w = run_w(fn[f"w_{k}"], mono)
+        assert [j for j, _ in w] == [tuple(j) for j in stencil]
+        for (j, wv), P in zip(w, orb["polys"]):
+            assert abs(wv - float(P(tuple(Fraction(float(v)) for v in u)))) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["fcc_6dir", "d4s_8dir"])
+def test_emitted_subregion_selector(name):
+    t = load(name)
+    text = open(f"{GENERATED}/{name}.inc").read()
+    body = _functions(text)["orbit"]
+    planes = [(tuple(int(v) for v in re.findall(r"AT\((-?\d+)\) \* up", ln)), ln) for ln in body if "code |=" in ln]
+    assert len(planes) == len(t.planes)
+    packed = int(re.search(r"\((\d+)ull >>", "\n".join(body)).group(1))
+    rng = np.random.default_rng(6)
+    for _ in range(400):
+        u = sorted(rng.uniform(0, t.D / 2, t.s), reverse=True)
+        if t.fold == "D" and rng.random() < 0.5:
+            u[-1] = -u[-1]
+        up = [Fraction(v) for v in u]
+        code = 0
+        for i, (nu, off) in enumerate(t.planes):
+            if sum(a * b for a, b in zip(nu, up)) - off >= 0:
+                code |= 1 << i
+        assert (packed >> (4 * code)) & 15 == orbit_of(t, up)
