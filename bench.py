@@ -6,7 +6,11 @@ FP32 queries, forward.  One step = one evaluation of all queries with the
 inputs resident in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c5|c1] [--dtype f32|bf16|f16]
-                    [--no-cpu] [--gpus 1]
+                    [--no-cpu] [--no-extra] [--order sorted|given] [--gpus 1]
+
+Besides the timed steps it reports the same step in the given query order,
+with a cold cache, a plain-copy bandwidth (whose kernel also calibrates the
+traffic counters), the CPU oracle on a bounded prefix and the accuracy there.
 """
 
 import argparse
@@ -52,10 +56,10 @@ def cpu_baseline(name, coeffs, X, target_s=8.0):
     cores = min(os.cpu_count() or 1, 16)
     coeffs64 = [np.asarray(c, dtype=np.float64) for c in coeffs]
     chunk = 256
-    # calibrate on one core
+    # calibrate on one core with one chunk (also the single-core rate)
     t0 = time.perf_counter()
-    _oracle_chunk((name, coeffs64, X[:64].astype(np.float64), chunk))
-    per_q = (time.perf_counter() - t0) / 64
+    _oracle_chunk((name, coeffs64, X[:chunk].astype(np.float64), chunk))
+    per_q = (time.perf_counter() - t0) / chunk
     n = int(min(len(X), max(256, target_s * cores / per_q)))
     n = (n // 256) * 256 or 256
     Xs = X[:n].astype(np.float64)
@@ -66,38 +70,93 @@ def cpu_baseline(name, coeffs, X, target_s=8.0):
         vals = np.concatenate(pool.map(_oracle_chunk, parts))
     dt = time.perf_counter() - t0
     rec = {"value": n / dt / 1e9, "unit": "Gsamples/s", "cores": cores, "kind": "oracle",
-           "sample": f"first {n} queries of the same workload, FP64 oracle, {dt:.1f} s"}
+           "sample": f"first {n} queries of the same workload, FP64 oracle, {dt:.1f} s",
+           "single_core_value": 1.0 / per_q / 1e9}
     return rec, np.arange(n), vals
 
 
 # ------------------------------------------------------------------ GPU legs
-def time_launches(fn, steps, warmup, torch, split=False):
-    """Run fn() `warmup` times, then time `steps` calls: wall time between two
-    synchronisations, plus durations from HIP events recorded on the stream the
-    library launches on (torch's current stream).  With split=True, fn records
-    a middle event between scheduling and evaluation; returns the evaluation
-    part's mean/median and the scheduling part's mean."""
+def time_phases(fn, steps, warmup, torch, nmarks=1, flush=None):
+    """Run fn() `warmup` times, then time `steps` calls.  fn(marks) records
+    the events in `marks` at its phase boundaries (nmarks of them), so every
+    step yields nmarks + 1 phase durations, measured with HIP events on the
+    stream the library launches on (torch's current stream).  With `flush`,
+    flush() runs before every step, outside the timed events and the wall
+    clock (cold-cache timing).  Returns (wall seconds over the timed steps,
+    per-phase mean seconds, per-phase median seconds)."""
     for _ in range(warmup):
-        fn()
+        fn(None)
     torch.cuda.synchronize()
     E = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    ev = [(E(), E(), E()) for _ in range(steps)]
+    ev = [[E() for _ in range(nmarks + 2)] for _ in range(steps)]
+    wall = 0.0
     t0 = time.perf_counter()
-    for a, m, b in ev:
-        a.record()
-        if split:
-            fn(m)
-        else:
-            fn()
-        b.record()
+    for row in ev:
+        if flush is not None:
+            torch.cuda.synchronize()
+            flush()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        row[0].record()
+        fn(row[1:-1])
+        row[-1].record()
+        if flush is not None:
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    if split:
-        per = [m.elapsed_time(b) / 1e3 for a, m, b in ev]
-        pre = [a.elapsed_time(m) / 1e3 for a, m, b in ev]
-        return wall, float(np.mean(per)), float(np.median(per)), float(np.mean(pre))
-    per = [a.elapsed_time(b) / 1e3 for a, m, b in ev]
-    return wall, float(np.mean(per)), float(np.median(per))
+    if flush is None:
+        wall = time.perf_counter() - t0
+    per = np.array([[row[i].elapsed_time(row[i + 1]) / 1e3 for i in range(nmarks + 1)] for row in ev])
+    return wall, per.mean(axis=0), np.median(per, axis=0)
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of 1 GiB: read + write bandwidth in GB/s.  Its
+    kernel also calibrates the FETCH_SIZE / WRITE_SIZE counters, since it
+    reads and writes exactly nbytes per dispatch."""
+    a = torch.ones(nbytes // 4, device="cuda")
+    b = torch.empty_like(a)
+    _, mean, _ = time_phases(lambda marks: b.copy_(a), reps, 3, torch, nmarks=0)
+    del a, b
+    return 2 * nbytes / float(mean[0]) / 1e9
+
+
+_SRC_DIRS = ("paper_2102_08514_amd/csrc", "paper_2102_08514_amd/csrc/generated")
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources and generated tables the library is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in _SRC_DIRS:
+        full = os.path.join(ROOT, d)
+        for name in sorted(os.listdir(full)):
+            if name.endswith((".hip", ".h", ".inc")):
+                h.update(name.encode())
+                with open(os.path.join(full, name), "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config, dtype):
+    """HBM bytes per launch of the dominant kernel from a committed counter
+    summary (a row `| traffic | <config> | <dtype> | <kernel> | <bytes> |
+    <digest> |`), or None when none exists for the current kernel sources."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    digest = kernel_source_digest()
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as fh:
+            for line in fh:
+                cells = [c.strip() for c in line.strip().strip("|").split("|")]
+                if len(cells) == 6 and cells[0] == "traffic" and cells[1] == config and cells[2] == dtype:
+                    if cells[5].strip("`") == digest:
+                        return {"bytes_per_launch": float(cells[4]), "kernel": cells[3].strip("`"),
+                                "source": f"profiles/{name}"}
+    return None
 
 
 def main():
@@ -108,6 +167,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the context legs (given order, cold cache, copy bandwidth)")
     ap.add_argument("--order", default="sorted", choices=["sorted", "given"],
                     help="evaluate in the library's scheduled order (timed) or in the given order")
     args = ap.parse_args()
@@ -125,6 +186,7 @@ def main():
     tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[args.dtype]
     if args.config == "c1":
         tdt = torch.float64
+    dname = {torch.float32: "f32", torch.bfloat16: "bf16", torch.float16: "f16", torch.float64: "f64"}[tdt]
     bytes_c = {torch.float32: 4, torch.bfloat16: 2, torch.float16: 2, torch.float64: 8}[tdt]
     log(f"[bench] generating {args.config} inputs")
     coeffs = I.coefficients(cfg)
@@ -139,21 +201,20 @@ def main():
     strm = torch.cuda.current_stream().cuda_stream
     from paper_2102_08514_amd import _lib as Lb
     given = None
-    sched_ms = None
+    X = None
+    mark = lambda marks, k: marks[k].record() if marks else None  # noqa: E731
     if args.config == "c3":
         W_, H_ = cfg.extra["rays"]
         S_ = cfg.extra["steps"]
         c, A = I.ray_params(cfg)
         n = W_ * H_ * S_
-        out = torch.empty(W_ * H_, 4, device="cuda")
         cf, Af = c.astype(np.float32), A.astype(np.float32)
+        phases = ["rays"]
 
-        def step(ev=None):
-            if ev is not None:
-                ev.record()
+        def step(marks, sched=None):
             sp.rays(vol, cf, Af, W_, H_, S_)
         bytes_per = Lq * bytes_c + 16.0 / S_                     # coefficients + per-ray output
-        X = None
+        kernels = "k_rays"
     else:
         X = I.queries(cfg)
         n = len(X)
@@ -168,52 +229,66 @@ def main():
             dldf = torch.empty(n, device="cuda")
             gradc = [torch.zeros(c.shape, device="cuda") for c in dev]
             gx = torch.empty(n, s, device="cuda")
+            phases = ["schedule", "forward", "backward"]
 
-            def step(ev=None, sched=use_sched):
+            def step(marks, sched=use_sched):
                 if sched:
                     Lb.lsp_schedule(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes, strm)
-                if ev is not None:
-                    ev.record()
+                mark(marks, 0)
                 loss.zero_()
+                # forward: f, dL/df, L and dL/dx; backward: dL/dc (scatter-add into zeroed arrays)
+                if sched:
+                    Lb.lsp_eval_mse_scheduled(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, ws.data_ptr(),
+                                              ws_bytes, f.data_ptr(), dldf.data_ptr(), gx.data_ptr(),
+                                              loss.data_ptr(), strm)
+                else:
+                    Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(),
+                                    dldf.data_ptr(), gx.data_ptr(), loss.data_ptr(), strm)
+                mark(marks, 1)
                 for g in gradc:
                     g.zero_()
                 if sched:
-                    Lb.lsp_eval_mse_scheduled(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, ws.data_ptr(),
-                                              ws_bytes, f.data_ptr(), dldf.data_ptr(), loss.data_ptr(), strm)
                     Lb.lsp_eval_adjoint_scheduled(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
-                                                  ws.data_ptr(), ws_bytes, [g.data_ptr() for g in gradc],
-                                                  gx.data_ptr(), strm)
+                                                  ws.data_ptr(), ws_bytes, [g.data_ptr() for g in gradc], None,
+                                                  strm)
                 else:
-                    Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(),
-                                    dldf.data_ptr(), loss.data_ptr(), strm)
                     Lb.lsp_eval_adjoint(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
-                                        [g.data_ptr() for g in gradc], gx.data_ptr(), strm)
-            # fwd: x + y + coefficients + f + dL/df; bwd: x + dL/df + coefficients (regather) +
-            # scatter (4 B each) + grad_x
-            bytes_per = (4 * s + 4 + Lq * bytes_c + 8) + (4 * s + 4 + Lq * bytes_c + Lq * 4 + 4 * s)
+                                        [g.data_ptr() for g in gradc], None, strm)
+            # fwd: x + y + coefficients + f + dL/df + dL/dx; bwd: x + dL/df + scatter (4 B per site)
+            bytes_fwd = 4 * s + 4 + Lq * bytes_c + 8 + 4 * s
+            bytes_bwd = 4 * s + 4 + Lq * 4
+            bytes_per = bytes_fwd + bytes_bwd
+            kernels = "forward + backward kernels (MSE forward with dL/dx, adjoint scatter)"
         else:
-            def step(ev=None, sched=use_sched):
+            phases = ["schedule", "forward"]
+
+            def step(marks, sched=use_sched):
                 if sched:
                     Lb.lsp_schedule(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes, strm)
-                if ev is not None:
-                    ev.record()
+                mark(marks, 0)
                 if sched:
                     Lb.lsp_eval_scheduled(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes,
                                           f.data_ptr(), None, strm)
                 else:
                     Lb.lsp_eval(sp.plan, vol.handle, x.data_ptr(), n, f.data_ptr(), None, strm)
             bytes_per = 4 * s + Lq * bytes_c + out_b
-        if use_sched:
+            kernels = "k_eval_binned" if use_sched else "k_eval"
+        if use_sched and not args.no_extra:
             # context: the same step on the queries in their given order
-            gw, gm, _ = time_launches(lambda ev=None: step(ev, sched=False), max(3, args.steps // 4), 1, torch)
-            given = {"ms_per_step": round(gw / max(3, args.steps // 4) * 1e3, 4),
-                     "value": round(n / (gw / max(3, args.steps // 4)) / 1e9, 4)}
+            k = max(3, args.steps // 4)
+            gw, _, _ = time_phases(lambda marks: step(marks, sched=False), k, 1, torch, nmarks=len(phases) - 1)
+            given = {"ms_per_step": round(gw / k * 1e3, 4), "value": round(n / (gw / k) / 1e9, 4)}
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps after {args.warmup} warm-up")
-    wall, mean_launch, med_launch, sched_mean = time_launches(step, args.steps, args.warmup, torch, split=True)
+    nm = len(phases) - 1
+    wall, pmean, pmed = time_phases(step, args.steps, args.warmup, torch, nmarks=nm)
     ms_per_step = wall / args.steps * 1e3
     value = n / (wall / args.steps) / 1e9
-    achieved = bytes_per * n / mean_launch / 1e9
+    # the roofline covers everything after the schedule: the evaluation kernels
+    ev_mean = float(pmean[1:].sum()) if nm else float(pmean[0])
+    ev_med = float(pmed[1:].sum()) if nm else float(pmed[0])
+    achieved = bytes_per * n / ev_mean / 1e9
+    traffic = measured_traffic(args.config, dname)
     rec = {
         "metric": "Gsamples/s fwd and fwd+bwd at stated max err vs FP64 oracle; % HBM roofline",
         "value": round(value, 4),
@@ -225,28 +300,46 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {torch.float32: "f32", torch.bfloat16: "bf16 storage, f32 math", torch.float16:
-                  "f16 storage, f32 math", torch.float64: "f64"}[tdt],
+        "dtype": {"f32": "f32", "bf16": "bf16 storage, f32 math", "f16": "f16 storage, f32 math",
+                  "f64": "f64"}[dname],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "spline": info["name"],
                    "n_samples": n, "lookups_per_sample": Lq, "volume_dims": list(cfg.dims),
                    "n_cosets": cfg.M, "passes": cfg.passes,
                    "order": "rays" if X is None else args.order},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "algorithmic_bytes_per_sample": round(bytes_per, 3),
-                     "eval_ms_mean": round(mean_launch * 1e3, 4), "eval_ms_median": round(med_launch * 1e3, 4)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                     "kernel": kernels, "algorithmic_bytes_per_sample": round(bytes_per, 3),
+                     "samples_per_launch": n,
+                     "eval_ms_mean": round(ev_mean * 1e3, 4), "eval_ms_median": round(ev_med * 1e3, 4)},
+        "phases_ms_mean": {p: round(float(v) * 1e3, 4) for p, v in zip(phases, pmean)},
+        "kernel_source_digest": kernel_source_digest(),
     }
-    if sched_mean is not None and X is not None and args.order == "sorted":
-        rec["schedule_ms_mean"] = round(sched_mean * 1e3, 4)
+    if traffic is not None:
+        rec["roofline"]["traffic_source"] = traffic["source"]
+        rec["roofline"]["traffic_kernel"] = traffic["kernel"]
+    if cfg.passes == "mse":
+        t_sched, t_fwd, t_bwd = (float(v) for v in pmean)
+        rec["forward_only"] = {"value": round(n / (t_sched + t_fwd) / 1e9, 4), "unit": "Gsamples/s",
+                               "note": "schedule + forward phases of the same timed steps"}
+        rec["fwd_bwd_over_fwd"] = round((t_sched + t_fwd + t_bwd) / (t_sched + t_fwd), 3)
     if given is not None:
         rec["given_order"] = given
+    if not args.no_extra:
+        # cold cache: a 1 GiB write evicts the 256 MB MALL and every L2 before each step
+        junk = torch.empty(1 << 28, device="cuda")
+        k = max(3, args.steps // 4)
+        cw, cmean, _ = time_phases(step, k, 1, torch, nmarks=nm, flush=lambda: junk.fill_(1.0))
+        rec["cold_cache"] = {"ms_per_step": round(cw / k * 1e3, 4), "value": round(n / (cw / k) / 1e9, 4)}
+        del junk
+        rec["roofline"]["copy_gbs"] = round(copy_bandwidth(torch), 1)
     if not args.no_cpu and X is not None:
         log("[bench] CPU oracle leg")
         cb, idx, want = cpu_baseline(args.config, coeffs if tdt != torch.float32 else
                                      [c.astype(np.float32) for c in coeffs], X)
         rec["cpu_baseline"] = cb
-        got = f[:len(idx)].double().cpu().numpy() if cfg.passes != "mse" else f[:len(idx)].double().cpu().numpy()
+        got = f[:len(idx)].double().cpu().numpy()
         scale = max(float(np.abs(c).max()) for c in coeffs)
         err = np.abs(got - want) / scale
         rec["accuracy"] = {"max_err": float(err.max()), "rms_err": float(np.sqrt(np.mean(err ** 2))),

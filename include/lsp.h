@@ -108,9 +108,11 @@ lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void*
 
 /* Forward with a mean-squared-error head against targets y (N float32):
  * writes f, dL/df = 2 (f - y) / N, and adds L = sum (f - y)^2 / N to *loss
- * (float64; the caller zeroes it).  Float32 volumes only. */
+ * (float64; the caller zeroes it).  If dloss_dx is not NULL it also receives
+ * dL/dx = dL/df * grad f (N x s) -- the loss gradient for the queries, known
+ * already in the forward pass.  Float32/bf16/f16 volumes. */
 lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n, float* f,
-                        float* dloss_df, double* loss, void* stream);
+                        float* dloss_df, float* dloss_dx, double* loss, void* stream);
 
 /* Adjoint: for upstream gradients g (N float32) adds sum_q g_q phi(x_q - site)
  * into grad_c (M float32 device arrays shaped like the volume; the caller
@@ -142,9 +144,13 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
  * splines whose several sub-regions carry costly polynomials, the
  * sub-region -- an item is then one (query, coset) pair, so a wave evaluates
  * one polynomial set instead of predicating all of them (Sec. 4.3).  The
- * scheduled calls run one workgroup per brick, which (in 3-D) stages the
- * brick's coefficients plus the stencil halo in LDS; the adjoint accumulates
- * its scatter-add in LDS and flushes it once per brick.
+ * scheduled calls run one workgroup per unit (a brick, or a (brick, coset)
+ * pair for coset-split items), which in 3-D stages the unit's coefficients
+ * plus the stencil halo in LDS.  The scheduled adjoint accumulates its
+ * scatter-add in an LDS copy of the unit's region, stores it to a private
+ * slot of the workspace, and a gather pass sums the slots covering every site
+ * (no global atomics, fixed order per site; only queries outside the volume
+ * scatter with atomics).
  *
  * lsp_schedule_size: device workspace bytes for n queries (depends on the
  * plan, the volume dims and n).  lsp_schedule: fills that caller-owned,
@@ -152,16 +158,16 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
  * *_scheduled calls then evaluate the same x (same n) in that order; results
  * land at each query's own index, exactly as the unscheduled calls.
  * Errors: LSP_ERR_NULL, LSP_ERR_INVALID (workspace too small or misaligned,
- * n * cosets >= 2^32).  The adjoint's float additions into grad_c happen in
- * an unspecified order (LDS and global atomics). */
+ * n * cosets >= 2^32).  The adjoint's float additions into grad_c within a
+ * unit happen in an unspecified order (LDS atomics). */
 lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes);
 lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace, size_t ws_bytes,
                         void* stream);
 lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
                               size_t ws_bytes, void* f, void* grad_x, void* stream);
 lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n,
-                                  const void* workspace, size_t ws_bytes, float* f, float* dloss_df, double* loss,
-                                  void* stream);
+                                  const void* workspace, size_t ws_bytes, float* f, float* dloss_df, float* dloss_dx,
+                                  double* loss, void* stream);
 lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
                                       const void* workspace, size_t ws_bytes, float* const* grad_c, float* grad_x,
                                       void* stream);

@@ -55,7 +55,7 @@ def lib():
         L.lsp_vol_bind.argtypes = [vp, i32, P(vp), P(i64), P(vp)]
         L.lsp_vol_release.argtypes = [vp]
         L.lsp_eval.argtypes = [vp, vp, vp, i64, vp, vp, vp]
-        L.lsp_eval_mse.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp]
+        L.lsp_eval_mse.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp]
         L.lsp_eval_adjoint.argtypes = [vp, vp, vp, vp, i64, P(vp), vp, vp]
         L.lsp_eval_rays.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), i32, i32, i32, i64, i64, vp, vp,
                                     vp]
@@ -63,7 +63,7 @@ def lib():
         L.lsp_schedule_size.argtypes = [vp, vp, i64, P(sz)]
         L.lsp_schedule.argtypes = [vp, vp, vp, i64, vp, sz, vp]
         L.lsp_eval_scheduled.argtypes = [vp, vp, vp, i64, vp, sz, vp, vp, vp]
-        L.lsp_eval_mse_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp, vp, vp, vp]
+        L.lsp_eval_mse_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp, vp, vp, vp, vp]
         L.lsp_eval_adjoint_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, P(vp), vp, vp]
         L.lsp_status_string.argtypes = [i32]
         L.lsp_status_string.restype = ctypes.c_char_p
@@ -133,8 +133,9 @@ def lsp_eval(plan, vol, x_ptr, n, f_ptr, grad_ptr, stream):
     check(lib().lsp_eval(plan, vol, x_ptr, int(n), f_ptr, grad_ptr, stream), "lsp_eval")
 
 
-def lsp_eval_mse(plan, vol, x_ptr, y_ptr, n, f_ptr, dldf_ptr, loss_ptr, stream):
-    check(lib().lsp_eval_mse(plan, vol, x_ptr, y_ptr, int(n), f_ptr, dldf_ptr, loss_ptr, stream), "lsp_eval_mse")
+def lsp_eval_mse(plan, vol, x_ptr, y_ptr, n, f_ptr, dldf_ptr, dldx_ptr, loss_ptr, stream):
+    check(lib().lsp_eval_mse(plan, vol, x_ptr, y_ptr, int(n), f_ptr, dldf_ptr, dldx_ptr, loss_ptr, stream),
+          "lsp_eval_mse")
 
 
 def lsp_eval_adjoint(plan, vol, x_ptr, g_ptr, n, grad_c_ptrs, grad_x_ptr, stream):
@@ -164,9 +165,10 @@ def lsp_eval_scheduled(plan, vol, x_ptr, n, ws_ptr, ws_bytes, f_ptr, grad_ptr, s
           "lsp_eval_scheduled")
 
 
-def lsp_eval_mse_scheduled(plan, vol, x_ptr, y_ptr, n, ws_ptr, ws_bytes, f_ptr, dldf_ptr, loss_ptr, stream):
+def lsp_eval_mse_scheduled(plan, vol, x_ptr, y_ptr, n, ws_ptr, ws_bytes, f_ptr, dldf_ptr, dldx_ptr, loss_ptr,
+                           stream):
     check(lib().lsp_eval_mse_scheduled(plan, vol, x_ptr, y_ptr, int(n), ws_ptr, int(ws_bytes), f_ptr, dldf_ptr,
-                                       loss_ptr, stream), "lsp_eval_mse_scheduled")
+                                       dldx_ptr, loss_ptr, stream), "lsp_eval_mse_scheduled")
 
 
 def lsp_eval_adjoint_scheduled(plan, vol, x_ptr, g_ptr, n, ws_ptr, ws_bytes, grad_c_ptrs, grad_x_ptr, stream):

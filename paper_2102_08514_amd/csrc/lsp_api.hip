@@ -130,15 +130,25 @@ std::vector<int> canon_dir(std::vector<int> v) {
 // ---------------------------------------------------------------------------
 // binned schedule: geometry and workspace layout (bytes, 256-aligned):
 //   hist[tiles][nkeys] tot[nkeys+1] start[nkeys+1] partial[1024] recs[items]
-//   fpart[items] gpart[items][S]   (partials only for coset-split items)
-constexpr size_t kLdsBudget = 65536;   // per workgroup
+//   fpart[items] gpart[items][S]   (per-coset partials, coset-split splines)
+//   priv[units][region]            (the adjoint's per-unit LDS regions)
+constexpr size_t kLdsMax = 160 * 1024;    // LDS of one gfx950 workgroup
+constexpr size_t kLdsEval = 64 * 1024;    // keep several evaluation workgroups per CU
+// key histogram budget: 3-D bricks stay at 16^3 cells for the big volumes
+// (fewer, fuller bricks amortise the staged halo); 4-D needs the full LDS to
+// keep 8^4 bricks with sub-region keys
+template <class SP>
+constexpr size_t hist_budget() { return SP::S == 3 ? 64 * 1024 : kLdsMax; }
 
 struct Bin {
   BinGeom g;
   bool split;
   int at_size;
-  size_t off_hist, off_tot, off_start, off_partial, off_recs, off_fpart, off_gpart, bytes;
-  size_t lds_eval, lds_adj;
+  size_t region;        // floats per coset of a unit's staged region
+  size_t off_hist, off_tot, off_start, off_partial, off_recs, off_fpart, off_gpart, off_priv, bytes;
+  size_t lds_eval;      // 0: evaluate from global memory
+  size_t lds_adj;       // gradient region (+ coefficient region when staged)
+  bool adj_stage_c;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -153,6 +163,7 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   BinGeom& g = bn.g;
   g.n = n;
   g.items = bn.split ? n * SP::M : n;
+  g.upb = bn.split ? SP::M : 1;
   g.kpb = bn.split ? SP::K : 1;
   for (g.bshift = 3;; ++g.bshift) {
     unsigned long long nbr = 1;
@@ -160,14 +171,22 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
       g.nb[d] = (v->vol.dims[d] + (1 << g.bshift) - 1) >> g.bshift;
       nbr *= static_cast<unsigned long long>(g.nb[d]);
     }
-    if (nbr * g.kpb * 4 <= kLdsBudget) {
+    if (nbr * g.upb * g.kpb * 4 <= hist_budget<SP>()) {
       g.nbricks = static_cast<unsigned>(nbr);
-      g.nkeys = static_cast<unsigned>(nbr * g.kpb);
+      g.nunits = static_cast<unsigned>(nbr * g.upb);
+      g.nkeys = static_cast<unsigned>(nbr * g.upb * g.kpb);
       break;
     }
   }
   g.tiles = static_cast<int>(std::max<long long>(1, std::min<long long>(256, (g.items + 4095) / 4096)));
   g.tile_items = (g.items + g.tiles - 1) / g.tiles;
+  const int nc = bn.split ? 1 : SP::M;
+  bn.region = static_cast<size_t>(Staged<SP>::volume(1 << g.bshift));
+  const size_t eval_lds = nc * bn.region * bn.at_size;
+  bn.lds_eval = (SP::S == 3 && eval_lds <= kLdsEval) ? eval_lds : 0;
+  const size_t grad_lds = nc * bn.region * 4;
+  bn.adj_stage_c = SP::S == 3 && 2 * grad_lds <= kLdsMax;
+  bn.lds_adj = grad_lds * (bn.adj_stage_c ? 2 : 1);
   size_t o = 0;
   bn.off_hist = o; o = align256(o + 4ull * g.tiles * g.nkeys);
   bn.off_tot = o; o = align256(o + 4ull * (g.nkeys + 1));
@@ -176,10 +195,8 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   bn.off_recs = o; o = align256(o + sizeof(Rec<SP::S>) * static_cast<size_t>(g.items));
   bn.off_fpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items : 0));
   bn.off_gpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items * SP::S : 0));
+  bn.off_priv = o; o = align256(o + (grad_lds <= kLdsMax ? 4ull * g.nunits * nc * bn.region : 0));
   bn.bytes = o;
-  const size_t region = SP::S == 3 ? static_cast<size_t>(SP::M) * Staged<SP>::volume(1 << g.bshift) : 0;
-  bn.lds_eval = region * bn.at_size;
-  bn.lds_adj = region * 4 * 2;
   return bn;
 }
 
@@ -207,43 +224,48 @@ lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws,
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
-unsigned brick_grid(unsigned nbricks) { return 8u * ((nbricks + 7u) / 8u); }
+unsigned unit_grid(unsigned nunits) { return 8u * ((nunits + 7u) / 8u); }
 
 template <class SP, class CT, class AT, bool MSE>
-lsp_status launch_binned_eval(const lsp_vol_s* v, const float* x, int64_t n, const void* ws, AT* f, AT* grad,
-                              const float* y, float* dldf, double* loss, hipStream_t st) {
-  (void)x;
+lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT* f, AT* grad, const float* y,
+                              float* dldf, double* loss, hipStream_t st) {
   const Bin bn = make_bin<SP>(v, n);
   const BinGeom& g = bn.g;
   const char* base = static_cast<const char*>(ws);
   const unsigned* start = reinterpret_cast<const unsigned*>(base + bn.off_start);
   const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
   constexpr bool SPLIT = SplitPolicy<SP>::value;
-  constexpr bool STAGE = SP::S == 3;
   const float inv_n = 1.0f / static_cast<float>(n);
-  if (bn.lds_eval > kLdsBudget) return LSP_ERR_UNSUPPORTED;
+  const dim3 grid(unit_grid(g.nunits));
+  // 3-D: stage the unit's coefficients in LDS; 4-D: gather from global memory
+#define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                               \
+  hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_>), grid, dim3(256), bn.lds_eval, st, \
+                     v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss)
   if constexpr (SPLIT) {
-    AT* fpart = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_fpart);
-    AT* gpart = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_gpart);
-    if (grad) {
-      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, true, true, STAGE, false>), dim3(brick_grid(g.nbricks)),
-                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, fpart, gpart, y, inv_n, dldf, loss);
-      hipLaunchKernelGGL((k_combine<SP, AT, true, false>), dim3(std::min(grid_of(n), 1024u)), dim3(256), 0, st, fpart, gpart,
-                         static_cast<long long>(n), f, grad, y, inv_n, dldf, loss);
+    AT* fo = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_fpart);
+    AT* go = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_gpart);
+    if (bn.lds_eval) {
+      if (grad) LSP_EVAL_BINNED(true, true, false); else LSP_EVAL_BINNED(false, true, false);
     } else {
-      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, false, true, STAGE, false>), dim3(brick_grid(g.nbricks)),
-                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, fpart, gpart, y, inv_n, dldf, loss);
-      hipLaunchKernelGGL((k_combine<SP, AT, false, MSE>), dim3(std::min(grid_of(n), 1024u)), dim3(256), 0, st, fpart, gpart,
-                         static_cast<long long>(n), f, grad, y, inv_n, dldf, loss);
+      if (grad) LSP_EVAL_BINNED(true, false, false); else LSP_EVAL_BINNED(false, false, false);
     }
-  } else {
+    const dim3 cg(std::min(grid_of(n), 1024u));
     if (grad)
-      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, true, false, STAGE, false>), dim3(brick_grid(g.nbricks)),
-                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, f, grad, y, inv_n, dldf, loss);
+      hipLaunchKernelGGL((k_combine<SP, AT, true, MSE>), cg, dim3(256), 0, st, fo, go, static_cast<long long>(n), f,
+                         grad, y, inv_n, dldf, loss);
     else
-      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, false, false, STAGE, MSE>), dim3(brick_grid(g.nbricks)),
-                         dim3(256), bn.lds_eval, st, v->vol, g, recs, start, f, grad, y, inv_n, dldf, loss);
+      hipLaunchKernelGGL((k_combine<SP, AT, false, MSE>), cg, dim3(256), 0, st, fo, go, static_cast<long long>(n), f,
+                         grad, y, inv_n, dldf, loss);
+  } else {
+    AT* fo = f;
+    AT* go = grad;
+    if (bn.lds_eval) {
+      if (grad) LSP_EVAL_BINNED(true, true, MSE); else LSP_EVAL_BINNED(false, true, MSE);
+    } else {
+      if (grad) LSP_EVAL_BINNED(true, false, MSE); else LSP_EVAL_BINNED(false, false, MSE);
+    }
   }
+#undef LSP_EVAL_BINNED
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
@@ -252,8 +274,7 @@ lsp_status launch_eval(const lsp_vol_s* v, const float* x, int64_t n, const void
                        hipStream_t st) {
   AT* fo = static_cast<AT*>(f);
   AT* go = static_cast<AT*>(grad);
-  if (ws)
-    return launch_binned_eval<SP, CT, AT, false>(v, x, n, ws, fo, go, nullptr, nullptr, nullptr, st);
+  if (ws) return launch_binned_eval<SP, CT, AT, false>(v, n, ws, fo, go, nullptr, nullptr, nullptr, st);
   if (grad)
     hipLaunchKernelGGL((k_eval<SP, CT, AT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x,
                        static_cast<long long>(n), nullptr, fo, go);
@@ -277,21 +298,25 @@ lsp_status eval_spec(const lsp_vol_s* v, const float* x, int64_t n, const void* 
 
 template <class SP, class CT>
 lsp_status launch_mse(const lsp_vol_s* v, const float* x, const float* y, int64_t n, const void* ws, float* f,
-                      float* dldf, double* loss, hipStream_t st) {
+                      float* dldf, float* dldx, double* loss, hipStream_t st) {
   const float inv_n = 1.0f / static_cast<float>(n);
-  if (ws) return launch_binned_eval<SP, CT, float, true>(v, x, n, ws, f, nullptr, y, dldf, loss, st);
-  hipLaunchKernelGGL((k_eval_mse<SP, CT>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x, y,
-                     static_cast<long long>(n), nullptr, inv_n, f, dldf, loss);
+  if (ws) return launch_binned_eval<SP, CT, float, true>(v, n, ws, f, dldx, y, dldf, loss, st);
+  if (dldx)
+    hipLaunchKernelGGL((k_eval_mse<SP, CT, true>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x, y,
+                       static_cast<long long>(n), inv_n, f, dldf, dldx, loss);
+  else
+    hipLaunchKernelGGL((k_eval_mse<SP, CT, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, x, y,
+                       static_cast<long long>(n), inv_n, f, dldf, dldx, loss);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
 template <class SP>
 lsp_status mse_spec(const lsp_vol_s* v, const float* x, const float* y, int64_t n, const void* ws, float* f,
-                    float* dldf, double* loss, hipStream_t st) {
+                    float* dldf, float* dldx, double* loss, hipStream_t st) {
   switch (v->dtype) {
-    case LSP_F32: return launch_mse<SP, float>(v, x, y, n, ws, f, dldf, loss, st);
-    case LSP_BF16: return launch_mse<SP, bf16_t>(v, x, y, n, ws, f, dldf, loss, st);
-    case LSP_F16: return launch_mse<SP, f16_t>(v, x, y, n, ws, f, dldf, loss, st);
+    case LSP_F32: return launch_mse<SP, float>(v, x, y, n, ws, f, dldf, dldx, loss, st);
+    case LSP_BF16: return launch_mse<SP, bf16_t>(v, x, y, n, ws, f, dldf, dldx, loss, st);
+    case LSP_F16: return launch_mse<SP, f16_t>(v, x, y, n, ws, f, dldf, dldx, loss, st);
   }
   return LSP_ERR_DTYPE;
 }
@@ -312,21 +337,31 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   }
   const Bin bn = make_bin<SP>(v, n);
   const BinGeom& gm = bn.g;
+  if (bn.lds_adj / (bn.adj_stage_c ? 2 : 1) > kLdsMax) return LSP_ERR_UNSUPPORTED;
   const char* base = static_cast<const char*>(ws);
   const unsigned* start = reinterpret_cast<const unsigned*>(base + bn.off_start);
   const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
+  float* priv = reinterpret_cast<float*>(const_cast<char*>(base) + bn.off_priv);
   constexpr bool SPLIT = SplitPolicy<SP>::value;
-  constexpr bool STAGE = SP::S == 3;
-  const size_t lds = grad_x ? bn.lds_adj : bn.lds_adj / 2;
-  if (lds > kLdsBudget) return LSP_ERR_UNSUPPORTED;
   float* gx_out = grad_x;
   if constexpr (SPLIT) gx_out = reinterpret_cast<float*>(const_cast<char*>(base) + bn.off_gpart);
-  if (grad_x)
-    hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, STAGE>), dim3(brick_grid(gm.nbricks)), dim3(256), lds,
-                       st, v->vol, gv, gm, recs, start, g, gx_out);
-  else
-    hipLaunchKernelGGL((k_adjoint_binned<SP, CT, false, SPLIT, STAGE>), dim3(brick_grid(gm.nbricks)), dim3(256),
-                       lds, st, v->vol, gv, gm, recs, start, g, gx_out);
+  const dim3 grid(unit_grid(gm.nunits));
+  const size_t lds_g = bn.lds_adj / (bn.adj_stage_c ? 2 : 1);
+  if (grad_x) {
+    if (bn.adj_stage_c)
+      hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, true>), grid, dim3(512), bn.lds_adj, st, v->vol, gv,
+                         gm, recs, start, g, gx_out, priv);
+    else
+      hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
+                         recs, start, g, gx_out, priv);
+  } else {
+    hipLaunchKernelGGL((k_adjoint_binned<SP, CT, false, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
+                       recs, start, g, gx_out, priv);
+  }
+  long long sites = 1;
+  for (int d = 0; d < SP::S; ++d) sites *= v->vol.dims[d];
+  hipLaunchKernelGGL((k_adjoint_gather<SP, SPLIT>), dim3(grid_of(sites * SP::M)), dim3(256), 0, st, v->vol, gv, gm,
+                     start, priv, sites);
   if (SPLIT && grad_x)
     hipLaunchKernelGGL((k_combine_gx<SP>), dim3(grid_of(n * SP::S)), dim3(256), 0, st, gx_out,
                        static_cast<long long>(n), grad_x);
@@ -562,7 +597,7 @@ lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void*
 }
 
 lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n, float* f,
-                        float* dloss_df, double* loss, void* stream) {
+                        float* dloss_df, float* dloss_dx, double* loss, void* stream) {
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
@@ -570,7 +605,7 @@ lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float*
   if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, nullptr, f, dloss_df, loss, s)
+  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, nullptr, f, dloss_df, dloss_dx, loss, s)
 }
 
 lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
@@ -649,8 +684,8 @@ lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_
 }
 
 lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* y, int64_t n,
-                                  const void* workspace, size_t ws_bytes, float* f, float* dloss_df, double* loss,
-                                  void* stream) {
+                                  const void* workspace, size_t ws_bytes, float* f, float* dloss_df, float* dloss_dx,
+                                  double* loss, void* stream) {
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
@@ -659,7 +694,7 @@ lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, co
   if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, workspace, f, dloss_df, loss, s)
+  LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, workspace, f, dloss_df, dloss_dx, loss, s)
 }
 
 lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,

@@ -13,17 +13,22 @@
 //   3. k_bin_place  per tile, LDS cursors place each item's record
 //      (query coordinates + item id) at its sorted position; a tile's items of
 //      one key land contiguously;
-//   4. k_eval_binned / k_adjoint_binned: one workgroup per brick stages the
-//      brick's coefficients (plus the stencil halo, zero outside the volume)
-//      into LDS with coalesced loads, then evaluates its queries from LDS.
-//      The adjoint accumulates the scatter-add into an LDS copy of the same
-//      region and flushes it with one global atomic per touched site.
+//   4. k_eval_binned: one workgroup per unit (a brick, or a (brick, coset)
+//      pair for coset-split items) stages the unit's coefficients (plus the
+//      stencil halo, zero outside the volume) into LDS with coalesced loads,
+//      then evaluates its queries from LDS;
+//   5. k_adjoint_binned + k_adjoint_gather: the adjoint accumulates the
+//      scatter-add g * w into an LDS copy of the unit's region and stores it
+//      with plain coalesced writes to the unit's private slot; a gather pass
+//      then sums, for every site, the (at most 2^s) unit regions covering it.
+//      No global atomics and a fixed summation order per site.
 //
-// key = brick (linear, x fastest) * kpb + sub-region: for splines with several
-// sub-regions after the fold (K > 1) a work item is one (query, coset) pair,
-// and the items of one brick are grouped by sub-region, so a wave runs one
-// polynomial set instead of predicating all of them (Sec. 4.3).  Per-coset
-// results go to partial buffers and are summed by a combine kernel.
+// key = unit * kpb + sub-region, unit = brick (linear, x fastest) * upb + coset:
+// for splines whose several sub-regions (after the fold) carry costly
+// polynomials a work item is one (query, coset) pair and the items of a unit
+// are grouped by sub-region, so a wave runs one polynomial set instead of
+// predicating all of them (Sec. 4.3).  Per-coset results go to partial
+// buffers and are summed by a combine kernel.
 
 namespace lsp {
 
@@ -31,8 +36,10 @@ struct BinGeom {
   int bshift;           // brick edge B = 1 << bshift cells per axis
   int nb[kMaxDim];      // bricks per axis
   unsigned nbricks;
-  int kpb;              // keys per brick: 1, or K for coset-split items
-  unsigned nkeys;       // nbricks * kpb
+  int upb;              // units per brick: M for coset-split items, else 1
+  unsigned nunits;      // nbricks * upb
+  int kpb;              // keys per unit: K for coset-split items, else 1
+  unsigned nkeys;       // nunits * kpb
   int tiles;            // histogram tiles
   long long tile_items;
   long long n;          // queries
@@ -95,7 +102,8 @@ __device__ __forceinline__ unsigned item_key(const Vol& vol, const BinGeom& g, c
     brick += static_cast<unsigned>(b) * mul;
     mul *= static_cast<unsigned>(g.nb[d]);
   }
-  unsigned key = brick * static_cast<unsigned>(g.kpb);
+  const unsigned unit = brick * static_cast<unsigned>(g.upb) + (SPLIT ? static_cast<unsigned>(k) : 0u);
+  unsigned key = unit * static_cast<unsigned>(g.kpb);
   if constexpr (SPLIT) {
     Folded<SP, float> F;
     fold_query<SP, float>(xq, k, vol, F);
@@ -202,15 +210,15 @@ __device__ __forceinline__ unsigned rec_item(const Rec<SP::S>& r, float* xq) {
   }
 }
 
-// brick handled by this workgroup: each XCD (blocks are dealt round-robin to
-// the 8 XCDs) takes a contiguous run of bricks, so neighbouring bricks share
+// unit handled by this workgroup: each XCD (blocks are dealt round-robin to
+// the 8 XCDs) takes a contiguous run of units, so neighbouring bricks share
 // their halo in one L2
-__device__ __forceinline__ long long brick_of_block(unsigned nbricks) {
-  const unsigned per = (nbricks + 7u) / 8u;
+__device__ __forceinline__ long long unit_of_block(unsigned nunits) {
+  const unsigned per = (nunits + 7u) / 8u;
   const unsigned xcd = blockIdx.x & 7u, slot = blockIdx.x >> 3;
   if (slot >= per) return -1;
-  const unsigned b = xcd * per + slot;
-  return b < nbricks ? static_cast<long long>(b) : -1;
+  const unsigned u = xcd * per + slot;
+  return u < nunits ? static_cast<long long>(u) : -1;
 }
 
 // staged coefficient region of one brick
@@ -239,11 +247,13 @@ __device__ __forceinline__ void stage_info(const BinGeom& g, long long brick, St
   si.vol = st;
 }
 
+// stage cosets [k0, k0 + ncos) of the region into lds[(k - k0) * vol + r]
 template <class SP, class CT, class AT>
-__device__ __forceinline__ void stage_load(const Vol& vol, const StageInfo<SP, AT>& si, AT* lds) {
-  const int total = SP::M * si.vol;
+__device__ __forceinline__ void stage_load(const Vol& vol, const StageInfo<SP, AT>& si, int k0, int ncos, AT* lds) {
+  const int total = ncos * si.vol;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int k = e / si.vol;
+    const int kl = e / si.vol;
+    const int k = k0 + kl;
     int r = e - k * si.vol;
     long long off = 0;
     bool in = true;
@@ -254,6 +264,7 @@ __device__ __forceinline__ void stage_load(const Vol& vol, const StageInfo<SP, A
       in = in && c >= 0 && c < vol.dims[d];
       off += static_cast<long long>(c) * vol.stride[d];
     }
+    (void)kl;
     const CT* base = static_cast<const CT*>(pick<SP::M>(vol.base, k));
     lds[e] = in ? load_coef<CT, AT>(base + off) : AT(0);
   }
@@ -337,9 +348,10 @@ struct ScatterLds {
   }
 };
 
-// one coset's psi (and folded gradient mapped back to x) from LDS or global
+// one coset's psi (and folded gradient mapped back to x) from LDS or global.
+// region: the LDS copy of coset k's part of the unit's region (or null).
 template <class SP, class CT, class AT, bool GRAD, bool STAGE>
-__device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP, AT>& si, const AT* lds, int k,
+__device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP, AT>& si, const AT* region, int k,
                                              const AT* xq, AT& f, AT* gx) {
   Folded<SP, AT> F;
   fold_query<SP, AT>(xq, k, vol, F);
@@ -349,7 +361,7 @@ __device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP,
   if constexpr (STAGE) staged = stageable<SP, AT>(si, F);
   if (staged) {
     GatherLds<SP, AT> g;
-    g.init(lds + k * si.vol, si, F);
+    g.init(region, si, F);
     SP::template b_any<AT>(ob, g, b);
   } else if (F.interior) {
     Gather<SP, CT, AT, false> g;
@@ -374,9 +386,28 @@ __device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP,
   }
 }
 
-// 4a. forward, one workgroup per brick.
-//   not SPLIT: f[q] (and grad[q]) directly; MSE also writes dL/df and adds the loss.
-//   SPLIT:     fpart[k * n + q] (and gpart) for the combine kernel.
+struct UnitRange {
+  long long unit, brick;
+  int kunit;            // the unit's coset (coset-split units)
+  unsigned lo, hi;      // its items in the sorted records
+};
+
+template <bool SPLIT>
+__device__ __forceinline__ bool unit_range(const BinGeom& g, const unsigned* start, UnitRange& u) {
+  u.unit = unit_of_block(g.nunits);
+  if (u.unit < 0) return false;
+  u.brick = u.unit / g.upb;
+  u.kunit = SPLIT ? static_cast<int>(u.unit - u.brick * g.upb) : 0;
+  const unsigned k0 = static_cast<unsigned>(u.unit) * g.kpb;
+  u.lo = start[k0];
+  u.hi = start[k0 + g.kpb];
+  return u.lo != u.hi;
+}
+
+// 4a. forward, one workgroup per unit.
+//   not SPLIT: f[q] (and grad[q]) directly.  SPLIT: fpart[k * n + q] (and
+//   gpart) for the combine kernel.  MSE (not SPLIT): also dL/df, and grad
+//   receives dL/dx = dL/df * grad f.
 template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE>
 __global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
                                                      const unsigned* __restrict__ start, AT* __restrict__ f,
@@ -384,19 +415,16 @@ __global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const R
                                                      float* __restrict__ dldf, double* __restrict__ loss) {
   extern __shared__ unsigned char smem[];
   AT* lds = reinterpret_cast<AT*>(smem);
-  const long long brick = brick_of_block(g.nbricks);
-  if (brick < 0) return;
-  const unsigned k0 = static_cast<unsigned>(brick) * g.kpb;
-  const unsigned lo = start[k0], hi = start[k0 + g.kpb];
-  if (lo == hi) return;
+  UnitRange u;
+  if (!unit_range<SPLIT>(g, start, u)) return;
   StageInfo<SP, AT> si;
-  stage_info<SP, AT>(g, brick, si);
+  stage_info<SP, AT>(g, u.brick, si);
   if constexpr (STAGE) {
-    stage_load<SP, CT, AT>(vol, si, lds);
+    stage_load<SP, CT, AT>(vol, si, SPLIT ? u.kunit : 0, SPLIT ? 1 : SP::M, lds);
     __syncthreads();
   }
   float r2 = 0.f;
-  for (unsigned t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+  for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
     float xf[SP::S];
     const unsigned item = rec_item<SP>(recs[t], xf);
     long long q;
@@ -419,23 +447,28 @@ __global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const R
       }
     } else {
 #pragma unroll
-      for (int kk = 0; kk < SP::M; ++kk) coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds, kk, xq, acc, gx);
+      for (int kk = 0; kk < SP::M; ++kk)
+        coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds + kk * si.vol, kk, xq, acc, gx);
       f[q] = acc;
-      if constexpr (GRAD) {
-#pragma unroll
-        for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = gx[d];
-      }
+      AT scale = AT(1);
       if constexpr (MSE) {
         const float r = static_cast<float>(acc) - y[q];
-        dldf[q] = 2.f * r * inv_n;
+        const float dl = 2.f * r * inv_n;
+        dldf[q] = dl;
         r2 += r * r;
+        scale = static_cast<AT>(dl);
+      }
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = scale * gx[d];
       }
     }
   }
   if constexpr (MSE && !SPLIT) mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
 
-// 4b. combine per-coset partials: f = sum_k fpart[k], grad likewise; optional MSE head
+// 4b. combine per-coset partials: f = sum_k fpart[k], grad likewise; with the
+// MSE head also dL/df, the loss, and grad = dL/df * grad f
 template <class SP, class AT, bool GRAD, bool MSE>
 __global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, const AT* __restrict__ gpart,
                                                  long long n, AT* __restrict__ f, AT* __restrict__ grad,
@@ -448,48 +481,51 @@ __global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, c
 #pragma unroll
     for (int k = 0; k < SP::M; ++k) acc += fpart[k * n + q];
     f[q] = acc;
+    AT scale = AT(1);
+    if constexpr (MSE) {
+      const float r = static_cast<float>(acc) - y[q];
+      const float dl = 2.f * r * inv_n;
+      dldf[q] = dl;
+      r2 += r * r;
+      scale = static_cast<AT>(dl);
+    }
     if constexpr (GRAD) {
 #pragma unroll
       for (int d = 0; d < SP::S; ++d) {
-        AT s = AT(0);
+        AT sum = AT(0);
 #pragma unroll
-        for (int k = 0; k < SP::M; ++k) s += gpart[(k * n + q) * SP::S + d];
-        grad[q * SP::S + d] = s;
+        for (int k = 0; k < SP::M; ++k) sum += gpart[(k * n + q) * SP::S + d];
+        grad[q * SP::S + d] = scale * sum;
       }
-    }
-    if constexpr (MSE) {
-      const float r = static_cast<float>(acc) - y[q];
-      dldf[q] = 2.f * r * inv_n;
-      r2 += r * r;
     }
   }
   if constexpr (MSE) mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
 
-// 5. adjoint, one workgroup per brick: scatter-add g * w into an LDS copy of
-// the brick's region, flush touched sites with one global atomic each.
-//   not SPLIT: grad_x[q] = g_q * grad f directly; SPLIT: gpart[k * n + q].
-template <class SP, class CT, bool GRADX, bool SPLIT, bool STAGE>
-__global__ void __launch_bounds__(256) k_adjoint_binned(Vol vol, GradVol gvol, BinGeom g,
+// 5a. adjoint, one workgroup per unit: scatter-add g * w into an LDS copy of
+// the unit's region, then store the region to the unit's private slot
+// priv[unit][ncos][vol] with plain writes (k_adjoint_gather sums the slots).
+// Items whose stencil leaves the region (queries outside the volume, clamped
+// to an edge brick) scatter with global atomics instead.
+//   GRADX, not SPLIT: grad_x[q] = g_q * grad f; SPLIT: gpart[k * n + q].
+template <class SP, class CT, bool GRADX, bool SPLIT, bool STAGE_C>
+__global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, BinGeom g,
                                                         const Rec<SP::S>* __restrict__ recs,
                                                         const unsigned* __restrict__ start,
-                                                        const float* __restrict__ gout, float* __restrict__ grad_x) {
+                                                        const float* __restrict__ gout, float* __restrict__ grad_x,
+                                                        float* __restrict__ priv) {
   extern __shared__ unsigned char smem[];
-  const long long brick = brick_of_block(g.nbricks);
-  if (brick < 0) return;
-  const unsigned k0 = static_cast<unsigned>(brick) * g.kpb;
-  const unsigned lo = start[k0], hi = start[k0 + g.kpb];
-  if (lo == hi) return;
+  UnitRange u;
+  if (!unit_range<SPLIT>(g, start, u)) return;
   StageInfo<SP, float> si;
-  stage_info<SP, float>(g, brick, si);
-  float* lds_g = reinterpret_cast<float*>(smem);                 // gradient region (M * vol)
-  float* lds_c = lds_g + (STAGE ? SP::M * si.vol : 0);            // coefficient region (GRADX)
-  if constexpr (STAGE) {
-    for (int e = threadIdx.x; e < SP::M * si.vol; e += blockDim.x) lds_g[e] = 0.f;
-    if constexpr (GRADX) stage_load<SP, CT, float>(vol, si, lds_c);
-    __syncthreads();
-  }
-  for (unsigned t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+  stage_info<SP, float>(g, u.brick, si);
+  constexpr int NC = SPLIT ? 1 : SP::M;
+  float* lds_g = reinterpret_cast<float*>(smem);        // gradient region (NC * vol)
+  float* lds_c = lds_g + NC * si.vol;                    // coefficient region (STAGE_C)
+  for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x) lds_g[e] = 0.f;
+  if constexpr (STAGE_C) stage_load<SP, CT, float>(vol, si, SPLIT ? u.kunit : 0, NC, lds_c);
+  __syncthreads();
+  for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
     float xq[SP::S];
     const unsigned item = rec_item<SP>(recs[t], xq);
     long long q;
@@ -500,18 +536,17 @@ __global__ void __launch_bounds__(256) k_adjoint_binned(Vol vol, GradVol gvol, B
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
 #pragma unroll
-    for (int kk = 0; kk < (SPLIT ? 1 : SP::M); ++kk) {
+    for (int kk = 0; kk < NC; ++kk) {
       const int kc = SPLIT ? k : kk;
       Folded<SP, float> F;
       fold_query<SP, float>(xq, kc, vol, F);
       const int ob = SP::template orbit<float>(F.up);
       float mono[SP::NMON];
       monomials<SP, float>(F.up, ob, mono);
-      bool staged = false;
-      if constexpr (STAGE) staged = stageable<SP, float>(si, F);
+      const bool staged = stageable<SP, float>(si, F);
       if (staged) {
         ScatterLds<SP> sc;
-        sc.init(lds_g + kc * si.vol, si, F, gq);
+        sc.init(lds_g + kk * si.vol, si, F, gq);
         SP::template w_any<float>(ob, sc, mono);
       } else if (F.interior) {
         Scatter<SP, false> sc;
@@ -524,9 +559,9 @@ __global__ void __launch_bounds__(256) k_adjoint_binned(Vol vol, GradVol gvol, B
       }
       if constexpr (GRADX) {
         float b[SP::NMON];
-        if (staged) {
+        if (STAGE_C && staged) {
           GatherLds<SP, float> gg;
-          gg.init(lds_c + kc * si.vol, si, F);
+          gg.init(lds_c + kk * si.vol, si, F);
           SP::template b_any<float>(ob, gg, b);
         } else if (F.interior) {
           Gather<SP, CT, float, false> gg;
@@ -553,25 +588,75 @@ __global__ void __launch_bounds__(256) k_adjoint_binned(Vol vol, GradVol gvol, B
       for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = gq * gx[d];
     }
   }
-  if constexpr (STAGE) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < SP::M * si.vol; e += blockDim.x) {
-      const float v = lds_g[e];
-      if (v == 0.f) continue;
-      const int k = e / si.vol;
-      int r = e - k * si.vol;
-      long long off = 0;
-      bool in = true;
+  __syncthreads();
+  float* out = priv + static_cast<size_t>(u.unit) * NC * si.vol;
+  for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x) out[e] = lds_g[e];
+}
+
+// 5b. grad_c[k][site] += sum of the private regions of the units covering the
+// site (per axis at most two bricks, since the region width is at most 2B)
+template <class SP, bool SPLIT>
+__global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, BinGeom g,
+                                                        const unsigned* __restrict__ start,
+                                                        const float* __restrict__ priv, long long sites) {
+  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= sites * SP::M) return;
+  const int k = static_cast<int>(e / sites);
+  const long long idx = e - static_cast<long long>(k) * sites;
+  const int B = 1 << g.bshift;
+  const int W = Staged<SP>::width(B);
+  int c[SP::S], blo[SP::S], bhi[SP::S];
+  long long rem = idx;
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) {
+    c[d] = static_cast<int>(rem % vol.dims[d]);
+    rem /= vol.dims[d];
+    // bricks b whose region [b B - 1 + OMIN, b B + B - 1 + OMAX] holds c
+    int lo = c[d] - (B - 1 + SP::OMAX);
+    lo = lo <= 0 ? 0 : (lo + B - 1) / B;
+    int hi = (c[d] + 1 - SP::OMIN) / B;
+    hi = hi >= g.nb[d] ? g.nb[d] - 1 : hi;
+    blo[d] = lo;
+    bhi[d] = hi;
+  }
+  constexpr int NC = SPLIT ? 1 : SP::M;
+  const int vol_r = Staged<SP>::volume(B);
+  float sum = 0.f;
+  int b[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) b[d] = blo[d];
+  for (;;) {
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) ok = ok && (b[d] <= bhi[d]);
+    if (ok) {
+      long long brick = 0, mul = 1;
+      int local = 0, ls = 1;
 #pragma unroll
       for (int d = 0; d < SP::S; ++d) {
-        const int c = si.org[d] + r % si.W;
-        r /= si.W;
-        in = in && c >= 0 && c < vol.dims[d];
-        off += static_cast<long long>(c) * vol.stride[d];
+        brick += static_cast<long long>(b[d]) * mul;
+        mul *= g.nb[d];
+        local += (c[d] - (b[d] * B - 1 + SP::OMIN)) * ls;
+        ls *= W;
       }
-      if (in) atomicAdd(pick<SP::M>(gvol.base, k) + off, v);
+      const long long unit = brick * g.upb + (SPLIT ? k : 0);
+      const unsigned k0 = static_cast<unsigned>(unit) * g.kpb;
+      if (start[k0] != start[k0 + g.kpb])
+        sum += priv[(static_cast<size_t>(unit) * NC + (SPLIT ? 0 : k)) * vol_r + local];
     }
+    // next combination (odometer over the brick ranges)
+    int d = 0;
+    for (; d < SP::S; ++d) {
+      if (b[d] < bhi[d]) {
+        ++b[d];
+        break;
+      }
+      b[d] = blo[d];
+    }
+    if (d == SP::S) break;
   }
+  float* gc = pick<SP::M>(gvol.base, k);
+  gc[idx] += sum;
 }
 
 // sum the per-coset grad_x partials of a split adjoint

@@ -456,28 +456,33 @@ __global__ void __launch_bounds__(256) k_mse_head(const float* __restrict__ f, c
   mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
 
-// forward fused with the MSE head (whole queries per lane)
-template <class SP, class CT>
+// forward fused with the MSE head (whole queries per lane); GRAD also writes
+// dL/dx = dL/df * grad f
+template <class SP, class CT, bool GRAD>
 __global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restrict__ x, const float* __restrict__ y,
-                                                  long long n, const unsigned* __restrict__ perm, float inv_n,
-                                                  float* __restrict__ f, float* __restrict__ dldf,
+                                                  long long n, float inv_n, float* __restrict__ f,
+                                                  float* __restrict__ dldf, float* __restrict__ dldx,
                                                   double* __restrict__ loss) {
-  const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   float r2 = 0.f;
-  if (t < n) {
-    long long q;
-    int k;
-    item_of<SP, false>(t, perm, q, k);
+  if (q < n) {
     float xq[SP::S];
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
     float acc = 0.f;
     float gx[SP::S];
 #pragma unroll
-    for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, float, false>(vol, kk, xq, acc, gx);
+    for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, float, GRAD>(vol, kk, xq, acc, gx);
     const float r = acc - y[q];
+    const float dl = 2.f * r * inv_n;
     f[q] = acc;
-    dldf[q] = 2.f * r * inv_n;
+    dldf[q] = dl;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) dldx[q * SP::S + d] = dl * gx[d];
+    }
     r2 = r * r;
   }
   mse_reduce(r2, static_cast<double>(inv_n), loss);

@@ -145,12 +145,17 @@ def test_mse_head(lsp, name):
     want = o.eval(c32, X.astype(np.float64))
     sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
     vol = sp.bind(to_dev(coeffs, torch.float32))
-    f, dldf, loss = sp.eval_mse(vol, torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda())
+    xd, yd = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda()
     n = len(X)
     r = want - y
-    assert normwise(f.cpu().numpy(), want, coeffs) <= 1e-5
-    np.testing.assert_allclose(dldf.cpu().numpy(), 2 * r / n, atol=2e-5 / n * 4)
-    assert abs(float(loss.item()) - float(np.mean(r * r))) <= 1e-5 * max(1.0, float(np.mean(r * r)))
+    _, gw = o.eval(c32, X.astype(np.float64), want_grad=True)
+    for sch in (None, sp.schedule(vol, xd)):
+        f, dldf, loss, dldx = sp.eval_mse(vol, xd, yd, schedule=sch, grad_x=True)
+        assert normwise(f.cpu().numpy(), want, coeffs) <= 1e-5
+        np.testing.assert_allclose(dldf.cpu().numpy(), 2 * r / n, atol=2e-5 / n * 4)
+        assert abs(float(loss.item()) - float(np.mean(r * r))) <= 1e-5 * max(1.0, float(np.mean(r * r)))
+        # dL/dx = dL/df * grad f
+        np.testing.assert_allclose(dldx.cpu().numpy(), (2 * r / n)[:, None] * gw, atol=1e-4 * 2 / n * 4)
 
 
 def test_autograd_backward_matches_adjoint(lsp):
