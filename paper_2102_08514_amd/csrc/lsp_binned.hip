@@ -247,26 +247,66 @@ __device__ __forceinline__ void stage_info(const BinGeom& g, long long brick, St
   si.vol = st;
 }
 
-// stage cosets [k0, k0 + ncos) of the region into lds[(k - k0) * vol + r]
+constexpr int kStageBatch = 8;
+
+// stage cosets [k0, k0 + ncos) of the region into lds[(k - k0) * vol + r],
+// zero outside the stored arrays.  A thread walks the region with a stride of
+// blockDim.x elements, carrying its per-axis position digit by digit instead
+// of dividing by W for every element; out-of-range elements load a valid
+// element and are replaced by zero.
 template <class SP, class CT, class AT>
 __device__ __forceinline__ void stage_load(const Vol& vol, const StageInfo<SP, AT>& si, int k0, int ncos, AT* lds) {
-  const int total = ncos * si.vol;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int kl = e / si.vol;
-    const int k = k0 + kl;
-    int r = e - k * si.vol;
-    long long off = 0;
-    bool in = true;
+  const int W = si.W, NT = static_cast<int>(blockDim.x);
+  int step[SP::S], start[SP::S];
+  {
+    int a = NT, b = static_cast<int>(threadIdx.x);
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) {
-      const int c = si.org[d] + r % si.W;
-      r /= si.W;
-      in = in && c >= 0 && c < vol.dims[d];
-      off += static_cast<long long>(c) * vol.stride[d];
+      step[d] = d + 1 < SP::S ? a % W : a;
+      start[d] = d + 1 < SP::S ? b % W : b;
+      a /= W;
+      b /= W;
     }
-    (void)kl;
-    const CT* base = static_cast<const CT*>(pick<SP::M>(vol.base, k));
-    lds[e] = in ? load_coef<CT, AT>(base + off) : AT(0);
+  }
+  // kStageBatch loads in flight per thread before their LDS writes
+  constexpr int U = kStageBatch;
+  for (int kl = 0; kl < ncos; ++kl) {
+    const CT* base = static_cast<const CT*>(pick<SP::M>(vol.base, k0 + kl));
+    AT* dst = lds + kl * si.vol;
+    int pos[SP::S];
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) pos[d] = start[d];
+    for (int e0 = static_cast<int>(threadIdx.x); e0 < si.vol; e0 += U * NT) {
+      AT v[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        bool in = e0 + u * NT < si.vol;
+        int off = 0;
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) {
+          const int c = si.org[d] + pos[d];
+          in = in && static_cast<unsigned>(c) < static_cast<unsigned>(vol.dims[d]);
+          off += c * vol.stride[d];
+        }
+        v[u] = load_coef<CT, AT>(base + (in ? off : 0));
+        ok[u] = in;
+        int carry = 0;
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) {
+          pos[d] += step[d] + carry;
+          if (d + 1 < SP::S) {
+            carry = pos[d] >= W;
+            pos[d] -= carry ? W : 0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * NT;
+        if (e < si.vol) dst[e] = ok[u] ? v[u] : AT(0);
+      }
+    }
   }
 }
 
@@ -293,58 +333,76 @@ __device__ __forceinline__ bool stageable(const StageInfo<SP, AT>& si, const Fol
 }
 
 // gather / scatter through the fold inside an LDS region
-template <class SP, class AT>
-struct GatherLds {
-  const AT* origin;
-  int st[SP::S];
-  __device__ __forceinline__ void init(const AT* region, const StageInfo<SP, AT>& si, const Folded<SP, AT>& F) {
+// Byte offsets of the folded stencil inside an LDS region.  A site J (folded
+// frame) sits at  origin + sum_r J_r st_r  elements, with st_r the signed
+// stride of folded axis r.  Per axis the multiples J st_r are tabulated once
+// per query (one add per entry), so a site's address is one three-input add
+// of table entries instead of a multiply-add chain per site.
+template <class SP, int ESIZE>
+struct FoldedOffsets {
+  static constexpr int JLO = SP::OMIN < 1 - SP::OMAX ? SP::OMIN : 1 - SP::OMAX;
+  static constexpr int JHI = SP::OMAX > 1 - SP::OMIN ? SP::OMAX : 1 - SP::OMIN;
+  static constexpr int NJ = JHI - JLO + 1;
+  unsigned p[SP::S][NJ];   // p[r][J - JLO] = J st_r (bytes); axis 0 also carries the origin
+
+  template <class AT>
+  __device__ __forceinline__ void init(const StageInfo<SP, AT>& si, const Folded<SP, AT>& F) {
     int off = 0;
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) off += (F.i[d] - si.org[d]) * si.ls[d];
+    int st[SP::S];
 #pragma unroll
     for (int r = 0; r < SP::S; ++r) {
       const int s = lds_stride<SP, AT>(si, F.ax[r]);
-      st[r] = F.sg[r] > 0 ? s : -s;
+      st[r] = F.sg[r] > 0 ? s * ESIZE : -s * ESIZE;
       if (F.sg[r] < 0) off += s;
     }
-    origin = region + off;
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const unsigned z = r == 0 ? static_cast<unsigned>(off * ESIZE) : 0u;
+      p[r][-JLO] = z;
+#pragma unroll
+      for (int j = -JLO + 1; j < NJ; ++j) p[r][j] = p[r][j - 1] + static_cast<unsigned>(st[r]);
+#pragma unroll
+      for (int j = -JLO - 1; j >= 0; --j) p[r][j] = p[r][j + 1] - static_cast<unsigned>(st[r]);
+    }
+  }
+  template <int J0, int J1, int J2, int J3>
+  __device__ __forceinline__ unsigned at() const {
+    unsigned a = p[0][J0 - JLO] + p[1][J1 - JLO] + p[2][J2 - JLO];
+    if constexpr (SP::S == 4) a += p[3][J3 - JLO];
+    return a;
+  }
+};
+
+template <class SP, class AT>
+struct GatherLds {
+  const char* region;
+  FoldedOffsets<SP, sizeof(AT)> o;
+  __device__ __forceinline__ void init(const AT* region_, const StageInfo<SP, AT>& si, const Folded<SP, AT>& F) {
+    region = reinterpret_cast<const char*>(region_);
+    o.init(si, F);
   }
   template <int J0, int J1, int J2, int J3 = 0>
   __device__ __forceinline__ AT c() const {
-    constexpr int J[4] = {J0, J1, J2, J3};
-    int off = 0;
-#pragma unroll
-    for (int r = 0; r < SP::S; ++r) off += J[r] * st[r];
-    return origin[off];
+    return *reinterpret_cast<const AT*>(region + o.template at<J0, J1, J2, J3>());
   }
 };
 
 template <class SP>
 struct ScatterLds {
-  float* origin;
-  int st[SP::S];
+  char* region;
+  FoldedOffsets<SP, sizeof(float)> o;
   float g;
-  __device__ __forceinline__ void init(float* region, const StageInfo<SP, float>& si, const Folded<SP, float>& F,
+  __device__ __forceinline__ void init(float* region_, const StageInfo<SP, float>& si, const Folded<SP, float>& F,
                                        float gq) {
-    int off = 0;
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) off += (F.i[d] - si.org[d]) * si.ls[d];
-#pragma unroll
-    for (int r = 0; r < SP::S; ++r) {
-      const int s = lds_stride<SP, float>(si, F.ax[r]);
-      st[r] = F.sg[r] > 0 ? s : -s;
-      if (F.sg[r] < 0) off += s;
-    }
-    origin = region + off;
+    region = reinterpret_cast<char*>(region_);
+    o.init(si, F);
     g = gq;
   }
   template <int J0, int J1, int J2, int J3 = 0>
   __device__ __forceinline__ void put(float w) {
-    constexpr int J[4] = {J0, J1, J2, J3};
-    int off = 0;
-#pragma unroll
-    for (int r = 0; r < SP::S; ++r) off += J[r] * st[r];
-    atomicAdd(origin + off, g * w);
+    atomicAdd(reinterpret_cast<float*>(region + o.template at<J0, J1, J2, J3>()), g * w);
   }
 };
 
@@ -424,9 +482,13 @@ __global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const R
     __syncthreads();
   }
   float r2 = 0.f;
+  // the next record is loaded while this one is evaluated
+  Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, u.hi - 1)];
   for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
+    const Rec<SP::S> nxt = recs[min(t + blockDim.x, u.hi - 1)];
     float xf[SP::S];
-    const unsigned item = rec_item<SP>(recs[t], xf);
+    const unsigned item = rec_item<SP>(cur, xf);
+    cur = nxt;
     long long q;
     int k;
     split_item<SP, SPLIT>(item, q, k);
@@ -525,13 +587,24 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
   for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x) lds_g[e] = 0.f;
   if constexpr (STAGE_C) stage_load<SP, CT, float>(vol, si, SPLIT ? u.kunit : 0, NC, lds_c);
   __syncthreads();
+  // the next record and its upstream gradient are loaded one query ahead
+  Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, u.hi - 1)];
+  float gcur;
+  {
+    float xs[SP::S];
+    long long q0;
+    int k0;
+    split_item<SP, SPLIT>(rec_item<SP>(cur, xs), q0, k0);
+    gcur = gout[q0];
+  }
   for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
+    const Rec<SP::S> nxt = recs[min(t + blockDim.x, u.hi - 1)];
     float xq[SP::S];
-    const unsigned item = rec_item<SP>(recs[t], xq);
+    const unsigned item = rec_item<SP>(cur, xq);
     long long q;
     int k;
     split_item<SP, SPLIT>(item, q, k);
-    const float gq = gout[q];
+    const float gq = gcur;
     float gx[SP::S];
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
@@ -587,6 +660,14 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
 #pragma unroll
       for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = gq * gx[d];
     }
+    {
+      float xs[SP::S];
+      long long qn;
+      int kn;
+      split_item<SP, SPLIT>(rec_item<SP>(nxt, xs), qn, kn);
+      gcur = gout[qn];
+    }
+    cur = nxt;
   }
   __syncthreads();
   float* out = priv + static_cast<size_t>(u.unit) * NC * si.vol;
