@@ -134,6 +134,7 @@ std::vector<int> canon_dir(std::vector<int> v) {
 //   priv[units][region]            (the adjoint's per-unit LDS regions)
 constexpr size_t kLdsMax = 160 * 1024;    // LDS of one gfx950 workgroup
 constexpr size_t kLdsEval = 64 * 1024;    // keep several evaluation workgroups per CU
+constexpr int kAbsMaxParts = 1024;         // blocks of the max |g| reduction
 // key histogram budget: 3-D bricks stay at 16^3 cells for the big volumes
 // (fewer, fuller bricks amortise the staged halo); 4-D needs the full LDS to
 // keep 8^4 bricks with sub-region keys
@@ -147,8 +148,10 @@ struct Bin {
   size_t region;        // floats per coset of a unit's staged region
   size_t off_hist, off_tot, off_start, off_partial, off_recs, off_fpart, off_gpart, off_priv, bytes;
   size_t lds_eval;      // 0: evaluate from global memory
-  size_t lds_adj;       // gradient region (+ coefficient region when staged)
+  size_t lds_adj;       // fixed-point gradient region (+ coefficient region when staged)
+  size_t lds_adj_g;     // fixed-point gradient region alone
   bool adj_stage_c;
+  size_t off_gmax;      // max |g| partials and result (the adjoint's fixed-point scale)
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -183,10 +186,14 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   const int nc = bn.split ? 1 : SP::M;
   bn.region = static_cast<size_t>(Staged<SP>::volume(1 << g.bshift));
   const size_t eval_lds = nc * bn.region * bn.at_size;
-  bn.lds_eval = (SP::S == 3 && eval_lds <= kLdsEval) ? eval_lds : 0;
-  const size_t grad_lds = nc * bn.region * 4;
-  bn.adj_stage_c = SP::S == 3 && 2 * grad_lds <= kLdsMax;
-  bn.lds_adj = grad_lds * (bn.adj_stage_c ? 2 : 1);
+  // 3-D: several small staged regions per CU; 4-D: one region of up to the
+  // whole LDS, evaluated by a 512-thread workgroup
+  bn.lds_eval = eval_lds <= (SP::S == 3 ? kLdsEval : kLdsMax) ? eval_lds : 0;
+  const size_t grad_lds = nc * bn.region * 8;   // 64-bit fixed-point accumulators
+  const size_t coef_lds = nc * bn.region * 4;
+  bn.adj_stage_c = SP::S == 3 && grad_lds + coef_lds <= kLdsMax;
+  bn.lds_adj_g = grad_lds;
+  bn.lds_adj = grad_lds + (bn.adj_stage_c ? coef_lds : 0);
   size_t o = 0;
   bn.off_hist = o; o = align256(o + 4ull * g.tiles * g.nkeys);
   bn.off_tot = o; o = align256(o + 4ull * (g.nkeys + 1));
@@ -196,6 +203,7 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   bn.off_fpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items : 0));
   bn.off_gpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items * SP::S : 0));
   bn.off_priv = o; o = align256(o + (grad_lds <= kLdsMax ? 4ull * g.nunits * nc * bn.region : 0));
+  bn.off_gmax = o; o = align256(o + 4ull * (kAbsMaxParts + 1));
   bn.bytes = o;
   return bn;
 }
@@ -237,10 +245,11 @@ lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT*
   constexpr bool SPLIT = SplitPolicy<SP>::value;
   const float inv_n = 1.0f / static_cast<float>(n);
   const dim3 grid(unit_grid(g.nunits));
-  // 3-D: stage the unit's coefficients in LDS; 4-D: gather from global memory
-#define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                               \
-  hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_>), grid, dim3(256), bn.lds_eval, st, \
-                     v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss)
+  // the unit's coefficients are staged in LDS when the region fits
+  constexpr int NT = SP::S == 3 ? 256 : 512;
+#define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                                 \
+  hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT), bn.lds_eval, \
+                     st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss)
   if constexpr (SPLIT) {
     AT* fo = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_fpart);
     AT* go = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_gpart);
@@ -337,7 +346,7 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   }
   const Bin bn = make_bin<SP>(v, n);
   const BinGeom& gm = bn.g;
-  if (bn.lds_adj / (bn.adj_stage_c ? 2 : 1) > kLdsMax) return LSP_ERR_UNSUPPORTED;
+  if (bn.lds_adj_g > kLdsMax) return LSP_ERR_UNSUPPORTED;
   const char* base = static_cast<const char*>(ws);
   const unsigned* start = reinterpret_cast<const unsigned*>(base + bn.off_start);
   const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
@@ -346,17 +355,23 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   float* gx_out = grad_x;
   if constexpr (SPLIT) gx_out = reinterpret_cast<float*>(const_cast<char*>(base) + bn.off_gpart);
   const dim3 grid(unit_grid(gm.nunits));
-  const size_t lds_g = bn.lds_adj / (bn.adj_stage_c ? 2 : 1);
+  const size_t lds_g = bn.lds_adj_g;
+  // max |g|: the power-of-two scale of the fixed-point regions
+  unsigned* gparts = reinterpret_cast<unsigned*>(const_cast<char*>(base) + bn.off_gmax);
+  unsigned* gmax = gparts + kAbsMaxParts;
+  const unsigned parts = std::min(grid_of(n), static_cast<unsigned>(kAbsMaxParts));
+  hipLaunchKernelGGL(k_absmax_partial, dim3(parts), dim3(256), 0, st, g, static_cast<long long>(n), gparts);
+  hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(1024), 0, st, gparts, static_cast<int>(parts), gmax);
   if (grad_x) {
     if (bn.adj_stage_c)
       hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, true>), grid, dim3(512), bn.lds_adj, st, v->vol, gv,
-                         gm, recs, start, g, gx_out, priv);
+                         gm, recs, start, g, gx_out, priv, gmax);
     else
       hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
-                         recs, start, g, gx_out, priv);
+                         recs, start, g, gx_out, priv, gmax);
   } else {
     hipLaunchKernelGGL((k_adjoint_binned<SP, CT, false, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
-                       recs, start, g, gx_out, priv);
+                       recs, start, g, gx_out, priv, gmax);
   }
   long long sites = 1;
   for (int d = 0; d < SP::S; ++d) sites *= v->vol.dims[d];

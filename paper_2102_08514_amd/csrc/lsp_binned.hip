@@ -18,10 +18,12 @@
 //      stencil halo, zero outside the volume) into LDS with coalesced loads,
 //      then evaluates its queries from LDS;
 //   5. k_adjoint_binned + k_adjoint_gather: the adjoint accumulates the
-//      scatter-add g * w into an LDS copy of the unit's region and stores it
-//      with plain coalesced writes to the unit's private slot; a gather pass
-//      then sums, for every site, the (at most 2^s) unit regions covering it.
-//      No global atomics and a fixed summation order per site.
+//      scatter-add g * w into an LDS copy of the unit's region, in 64-bit
+//      fixed point scaled by a power of two from max |g| (k_absmax_*), and
+//      stores it as floats with plain coalesced writes to the unit's private
+//      slot; a gather pass then sums, for every site, the (at most 2^s) unit
+//      regions covering it.  No global atomics, no float atomics, and the
+//      result does not depend on the order of the additions.
 //
 // key = unit * kpb + sub-region, unit = brick (linear, x fastest) * upb + coset:
 // for splines whose several sub-regions (after the fold) carry costly
@@ -64,8 +66,12 @@ template <> struct Rec<3> { float4 a; };             // x0 x1 x2 | item
 template <> struct Rec<4> { float4 a; uint4 b; };    // x0..x3 | item
 
 template <class SP> struct Staged {
-  // per coset the staged cells are [b B - 1 + OMIN, b B + B - 1 + OMAX] per axis
-  __host__ __device__ static constexpr int width(int B) { return B + 1 + SP::OMAX - SP::OMIN; }
+  // Per coset the staged cells are [b B - MARGIN + OMIN, b B + B - 1 + OMAX]
+  // per axis.  A whole-query item is binned by its coset-0 cell, and another
+  // coset's cell index can be one less (MARGIN = 1); a (query, coset) item is
+  // binned by its own coset's cell (MARGIN = 0).
+  static constexpr int MARGIN = SplitPolicy<SP>::value ? 0 : 1;
+  __host__ __device__ static constexpr int width(int B) { return B + MARGIN + SP::OMAX - SP::OMIN; }
   __host__ __device__ static constexpr int volume(int B) {
     int v = 1;
     for (int d = 0; d < SP::S; ++d) v *= width(B);
@@ -118,6 +124,9 @@ __device__ __forceinline__ void load_x(const float* __restrict__ x, long long q,
   for (int d = 0; d < SP::S; ++d) xq[d] = x[q * SP::S + d];
 }
 
+// items per thread whose query loads are in flight together
+constexpr int kBinBatch = 4;
+
 // 1. per-tile histogram of keys (dynamic LDS: nkeys counters)
 template <class SP, bool SPLIT>
 __global__ void __launch_bounds__(1024) k_bin_hist(Vol vol, BinGeom g, const float* __restrict__ x,
@@ -127,13 +136,20 @@ __global__ void __launch_bounds__(1024) k_bin_hist(Vol vol, BinGeom g, const flo
   __syncthreads();
   const long long t0 = static_cast<long long>(blockIdx.x) * g.tile_items;
   const long long t1 = t0 + g.tile_items < g.items ? t0 + g.tile_items : g.items;
-  for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-    long long q;
-    int k;
-    split_item<SP, SPLIT>(t, q, k);
-    float xq[SP::S];
-    load_x<SP>(x, q, xq);
-    atomicAdd(cnt + item_key<SP, SPLIT>(vol, g, xq, k), 1u);
+  constexpr int U = kBinBatch;
+  for (long long tb = t0 + threadIdx.x; tb < t1; tb += U * blockDim.x) {
+    float xq[U][SP::S];
+    int kk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long t = tb + static_cast<long long>(u) * blockDim.x;
+      long long q;
+      split_item<SP, SPLIT>(t < t1 ? t : t0, q, kk[u]);
+      load_x<SP>(x, q, xq[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tb + static_cast<long long>(u) * blockDim.x < t1) atomicAdd(cnt + item_key<SP, SPLIT>(vol, g, xq[u], kk[u]), 1u);
   }
   __syncthreads();
   unsigned* out = hist + static_cast<size_t>(blockIdx.x) * g.nkeys;
@@ -181,21 +197,35 @@ __global__ void __launch_bounds__(1024) k_bin_place(Vol vol, BinGeom g, const fl
   __syncthreads();
   const long long t0 = static_cast<long long>(blockIdx.x) * g.tile_items;
   const long long t1 = t0 + g.tile_items < g.items ? t0 + g.tile_items : g.items;
-  for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-    long long q;
-    int k;
-    split_item<SP, SPLIT>(t, q, k);
-    float xq[SP::S];
-    load_x<SP>(x, q, xq);
-    const unsigned pos = atomicAdd(cur + item_key<SP, SPLIT>(vol, g, xq, k), 1u);
-    Rec<SP::S> r;
-    if constexpr (SP::S == 3) {
-      r.a = make_float4(xq[0], xq[1], xq[2], __uint_as_float(static_cast<unsigned>(t)));
-    } else {
-      r.a = make_float4(xq[0], xq[1], xq[2], xq[3]);
-      r.b = make_uint4(static_cast<unsigned>(t), 0u, 0u, 0u);
+  constexpr int U = kBinBatch;
+  for (long long tb = t0 + threadIdx.x; tb < t1; tb += U * blockDim.x) {
+    float xq[U][SP::S];
+    int kk[U];
+    unsigned pos[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long t = tb + static_cast<long long>(u) * blockDim.x;
+      long long q;
+      split_item<SP, SPLIT>(t < t1 ? t : t0, q, kk[u]);
+      load_x<SP>(x, q, xq[u]);
     }
-    recs[pos] = r;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (tb + static_cast<long long>(u) * blockDim.x < t1)
+        pos[u] = atomicAdd(cur + item_key<SP, SPLIT>(vol, g, xq[u], kk[u]), 1u);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long t = tb + static_cast<long long>(u) * blockDim.x;
+      if (t >= t1) continue;
+      Rec<SP::S> r;
+      if constexpr (SP::S == 3) {
+        r.a = make_float4(xq[u][0], xq[u][1], xq[u][2], __uint_as_float(static_cast<unsigned>(t)));
+      } else {
+        r.a = make_float4(xq[u][0], xq[u][1], xq[u][2], xq[u][3]);
+        r.b = make_uint4(static_cast<unsigned>(t), 0u, 0u, 0u);
+      }
+      recs[pos[u]] = r;
+    }
   }
 }
 
@@ -208,6 +238,16 @@ __device__ __forceinline__ unsigned rec_item(const Rec<SP::S>& r, float* xq) {
     xq[0] = r.a.x; xq[1] = r.a.y; xq[2] = r.a.z; xq[3] = r.a.w;
     return r.b.x;
   }
+}
+
+// query index of a record's item
+template <class SP, bool SPLIT>
+__device__ __forceinline__ long long rec_query(const Rec<SP::S>& r) {
+  float xs[SP::S];
+  long long q;
+  int k;
+  split_item<SP, SPLIT>(rec_item<SP>(r, xs), q, k);
+  return q;
 }
 
 // unit handled by this workgroup: each XCD (blocks are dealt round-robin to
@@ -240,7 +280,7 @@ __device__ __forceinline__ void stage_info(const BinGeom& g, long long brick, St
   for (int d = 0; d < SP::S; ++d) {
     const int b = static_cast<int>(rem % g.nb[d]);
     rem /= g.nb[d];
-    si.org[d] = b * B - 1 + SP::OMIN;
+    si.org[d] = b * B - Staged<SP>::MARGIN + SP::OMIN;
     si.ls[d] = st;
     st *= si.W;
   }
@@ -389,22 +429,50 @@ struct GatherLds {
   }
 };
 
+// Fixed-point value of a float with |v| < 2^51, rounded to the nearest
+// integer: v = hi 2^24 + lo with hi = trunc(v 2^-24); the split is exact, so
+// the only rounding is that of lo.
+__device__ __forceinline__ long long to_fixed(float v) {
+  const float hi = truncf(v * 0x1p-24f);
+  const float lo = fmaf(hi, -0x1p24f, v);
+  return (static_cast<long long>(static_cast<int>(hi)) << 24) + static_cast<long long>(__float2int_rn(lo));
+}
+
+// Scatter-add into an LDS region of 64-bit fixed-point accumulators: gs is
+// g_q times the unit's power-of-two scale.  Integer LDS atomics are an order
+// of magnitude faster than float ones on this hardware, and integer sums do
+// not depend on the order of the additions.
 template <class SP>
 struct ScatterLds {
   char* region;
-  FoldedOffsets<SP, sizeof(float)> o;
-  float g;
-  __device__ __forceinline__ void init(float* region_, const StageInfo<SP, float>& si, const Folded<SP, float>& F,
-                                       float gq) {
+  FoldedOffsets<SP, 8> o;
+  float gs;
+  __device__ __forceinline__ void init(unsigned long long* region_, const StageInfo<SP, float>& si,
+                                       const Folded<SP, float>& F, float gscaled) {
     region = reinterpret_cast<char*>(region_);
     o.init(si, F);
-    g = gq;
+    gs = gscaled;
   }
   template <int J0, int J1, int J2, int J3 = 0>
   __device__ __forceinline__ void put(float w) {
-    atomicAdd(reinterpret_cast<float*>(region + o.template at<J0, J1, J2, J3>()), g * w);
+    atomicAdd(reinterpret_cast<unsigned long long*>(region + o.template at<J0, J1, J2, J3>()),
+              static_cast<unsigned long long>(to_fixed(gs * w)));
   }
 };
+
+// Power-of-two scale 2^shift of a unit's fixed-point region, shift = E - eg
+// with gmax < 2^eg.  |g w| <= gmax (the weights lie in [0, 1]) and a site
+// receives at most one term per item, so every scaled term is below 2^E and
+// a site's sum below items 2^E <= 2^61.  E = min(50, 61 - bit length of
+// items): terms are resolved to 2^-E of 2^eg (< 2 gmax).  The scaling is
+// applied with ldexp, so tiny or huge gradients cannot overflow a factor.
+__device__ __forceinline__ int unit_shift(unsigned items, float gmax) {
+  const int bits = 32 - __clz(static_cast<int>(items | 1u));
+  const int E = min(50, 61 - bits);
+  int eg = 0;
+  (void)frexpf(gmax > 0.f && gmax <= 3.402823466e38f ? gmax : 1.f, &eg);
+  return E - eg;
+}
 
 // one coset's psi (and folded gradient mapped back to x) from LDS or global.
 // region: the LDS copy of coset k's part of the unit's region (or null).
@@ -466,8 +534,8 @@ __device__ __forceinline__ bool unit_range(const BinGeom& g, const unsigned* sta
 //   not SPLIT: f[q] (and grad[q]) directly.  SPLIT: fpart[k * n + q] (and
 //   gpart) for the combine kernel.  MSE (not SPLIT): also dL/df, and grad
 //   receives dL/dx = dL/df * grad f.
-template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE>
-__global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE, int NT>
+__global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
                                                      const unsigned* __restrict__ start, AT* __restrict__ f,
                                                      AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
                                                      float* __restrict__ dldf, double* __restrict__ loss) {
@@ -484,11 +552,17 @@ __global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const R
   float r2 = 0.f;
   // the next record is loaded while this one is evaluated
   Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, u.hi - 1)];
+  float ycur = 0.f;
+  if constexpr (MSE && !SPLIT) ycur = y[rec_query<SP, SPLIT>(cur)];
   for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
     const Rec<SP::S> nxt = recs[min(t + blockDim.x, u.hi - 1)];
+    float ynxt = 0.f;
+    if constexpr (MSE && !SPLIT) ynxt = y[rec_query<SP, SPLIT>(nxt)];
     float xf[SP::S];
     const unsigned item = rec_item<SP>(cur, xf);
+    const float yq = ycur;
     cur = nxt;
+    ycur = ynxt;
     long long q;
     int k;
     split_item<SP, SPLIT>(item, q, k);
@@ -514,7 +588,7 @@ __global__ void __launch_bounds__(256) k_eval_binned(Vol vol, BinGeom g, const R
       f[q] = acc;
       AT scale = AT(1);
       if constexpr (MSE) {
-        const float r = static_cast<float>(acc) - y[q];
+        const float r = static_cast<float>(acc) - yq;
         const float dl = 2.f * r * inv_n;
         dldf[q] = dl;
         r2 += r * r;
@@ -575,36 +649,39 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
                                                         const Rec<SP::S>* __restrict__ recs,
                                                         const unsigned* __restrict__ start,
                                                         const float* __restrict__ gout, float* __restrict__ grad_x,
-                                                        float* __restrict__ priv) {
+                                                        float* __restrict__ priv, const unsigned* __restrict__ gmax_bits) {
   extern __shared__ unsigned char smem[];
   UnitRange u;
   if (!unit_range<SPLIT>(g, start, u)) return;
   StageInfo<SP, float> si;
   stage_info<SP, float>(g, u.brick, si);
   constexpr int NC = SPLIT ? 1 : SP::M;
-  float* lds_g = reinterpret_cast<float*>(smem);        // gradient region (NC * vol)
-  float* lds_c = lds_g + NC * si.vol;                    // coefficient region (STAGE_C)
-  for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x) lds_g[e] = 0.f;
+  unsigned long long* lds_g = reinterpret_cast<unsigned long long*>(smem);   // fixed-point gradient region
+  float* lds_c = reinterpret_cast<float*>(lds_g + NC * si.vol);               // coefficient region (STAGE_C)
+  const float gmax = __uint_as_float(*gmax_bits);
+  const int shift = unit_shift(u.hi - u.lo, gmax);
+  for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x) lds_g[e] = 0ull;
   if constexpr (STAGE_C) stage_load<SP, CT, float>(vol, si, SPLIT ? u.kunit : 0, NC, lds_c);
   __syncthreads();
-  // the next record and its upstream gradient are loaded one query ahead
-  Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, u.hi - 1)];
-  float gcur;
-  {
-    float xs[SP::S];
-    long long q0;
-    int k0;
-    split_item<SP, SPLIT>(rec_item<SP>(cur, xs), q0, k0);
-    gcur = gout[q0];
-  }
+  // software pipeline: records are loaded two queries ahead, the (randomly
+  // placed) upstream gradient one query ahead, so a whole query's work hides
+  // each load
+  const unsigned last = u.hi - 1;
+  Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, last)];
+  Rec<SP::S> nxt = recs[min(u.lo + threadIdx.x + blockDim.x, last)];
+  float gcur = gout[rec_query<SP, SPLIT>(cur)];
   for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
-    const Rec<SP::S> nxt = recs[min(t + blockDim.x, u.hi - 1)];
+    const Rec<SP::S> nn = recs[min(t + 2 * blockDim.x, last)];
+    const float gnxt = gout[rec_query<SP, SPLIT>(nxt)];
     float xq[SP::S];
     const unsigned item = rec_item<SP>(cur, xq);
     long long q;
     int k;
     split_item<SP, SPLIT>(item, q, k);
     const float gq = gcur;
+    cur = nxt;
+    nxt = nn;
+    gcur = gnxt;
     float gx[SP::S];
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
@@ -619,7 +696,7 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
       const bool staged = stageable<SP, float>(si, F);
       if (staged) {
         ScatterLds<SP> sc;
-        sc.init(lds_g + kk * si.vol, si, F, gq);
+        sc.init(lds_g + kk * si.vol, si, F, ldexpf(gq, shift));
         SP::template w_any<float>(ob, sc, mono);
       } else if (F.interior) {
         Scatter<SP, false> sc;
@@ -660,18 +737,48 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
 #pragma unroll
       for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = gq * gx[d];
     }
-    {
-      float xs[SP::S];
-      long long qn;
-      int kn;
-      split_item<SP, SPLIT>(rec_item<SP>(nxt, xs), qn, kn);
-      gcur = gout[qn];
-    }
-    cur = nxt;
   }
   __syncthreads();
+  // back to float; a non-finite upstream gradient makes the region NaN
+  const bool finite = gmax <= 3.402823466e38f;
   float* out = priv + static_cast<size_t>(u.unit) * NC * si.vol;
-  for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x) out[e] = lds_g[e];
+  for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x)
+    out[e] = finite ? ldexpf(static_cast<float>(static_cast<long long>(lds_g[e])), -shift) : __int_as_float(0x7fc00000);
+}
+
+// max |g| over the upstream gradient, as the bits of a non-negative float
+// (their unsigned order is the float order; NaN compares above +inf):
+// partial maxima per block, then one block reduces them.
+__device__ __forceinline__ unsigned block_max_u32(unsigned v, unsigned* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<unsigned>(__shfl_xor(static_cast<int>(v), off)));
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < static_cast<int>(blockDim.x / 64); ++w) v = max(v, red[w]);
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_absmax_partial(const float* __restrict__ gout, long long n,
+                                                        unsigned* __restrict__ partial) {
+  __shared__ unsigned red[4];
+  unsigned m = 0u;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    m = max(m, __float_as_uint(fabsf(gout[i])));
+  m = block_max_u32(m, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(1024) k_absmax_final(const unsigned* __restrict__ partial, int parts,
+                                                       unsigned* __restrict__ out) {
+  __shared__ unsigned red[16];
+  unsigned m = 0u;
+  for (int i = threadIdx.x; i < parts; i += blockDim.x) m = max(m, partial[i]);
+  m = block_max_u32(m, red);
+  if (threadIdx.x == 0) *out = m;
 }
 
 // 5b. grad_c[k][site] += sum of the private regions of the units covering the
@@ -692,10 +799,10 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
   for (int d = 0; d < SP::S; ++d) {
     c[d] = static_cast<int>(rem % vol.dims[d]);
     rem /= vol.dims[d];
-    // bricks b whose region [b B - 1 + OMIN, b B + B - 1 + OMAX] holds c
+    // bricks b whose region [b B - MARGIN + OMIN, b B + B - 1 + OMAX] holds c
     int lo = c[d] - (B - 1 + SP::OMAX);
     lo = lo <= 0 ? 0 : (lo + B - 1) / B;
-    int hi = (c[d] + 1 - SP::OMIN) / B;
+    int hi = (c[d] + Staged<SP>::MARGIN - SP::OMIN) / B;
     hi = hi >= g.nb[d] ? g.nb[d] - 1 : hi;
     blo[d] = lo;
     bhi[d] = hi;
@@ -717,7 +824,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
       for (int d = 0; d < SP::S; ++d) {
         brick += static_cast<long long>(b[d]) * mul;
         mul *= g.nb[d];
-        local += (c[d] - (b[d] * B - 1 + SP::OMIN)) * ls;
+        local += (c[d] - (b[d] * B - Staged<SP>::MARGIN + SP::OMIN)) * ls;
         ls *= W;
       }
       const long long unit = brick * g.upb + (SPLIT ? k : 0);
