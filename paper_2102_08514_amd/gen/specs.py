@@ -17,6 +17,10 @@ L_CC = I3
 L_BCC = [[-1, 1, 1], [1, -1, 1], [1, 1, -1]]
 L_FCC = [[0, 1, 1], [1, 0, 1], [1, 1, 0]]
 L_D4S = [[2, 0, 0, 1], [0, 2, 0, 1], [0, 0, 2, 1], [0, 0, 0, 1]]
+# the D4 lattice and its 8-direction spline of Sec. 5.2 (columns (+-1, +-1, +-1, 1))
+L_D4 = [[-1, 0, 0, 0], [1, 0, -1, -1], [0, -1, 0, 1], [0, -1, 1, 0]]
+XI_D4 = [[1, 1, 1, 1, -1, -1, -1, -1], [1, 1, -1, -1, 1, 1, -1, -1], [1, -1, 1, -1, 1, -1, 1, -1],
+         [1, 1, 1, 1, 1, 1, 1, 1]]
 I4 = [[int(a == b) for b in range(4)] for a in range(4)]
 HAD4_COLS = [list(r) for r in zip(*HAD4)]  # columns of the Hadamard matrix as rows
 
@@ -27,4 +31,5 @@ SPECS = {
     "bcc_quartic": ("SplineBccQuartic", L_BCC, _hcat(_scale(I3, 2), BCC_DIAG)),
     "fcc_6dir": ("SplineFcc6", L_FCC, [[1, -1, 1, 1, 0, 0], [1, 1, 0, 0, 1, -1], [0, 0, 1, -1, 1, 1]]),
     "d4s_8dir": ("SplineD4s8", L_D4S, _hcat(_scale(I4, 2), [list(r) for r in zip(*HAD4_COLS)])),
+    "d4_8dir": ("SplineD48", L_D4, XI_D4),
 }
