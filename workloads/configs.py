@@ -40,6 +40,14 @@ XI_FCC6 = np.array([[1, -1, 1, 1, 0, 0],
                     [1, 1, 0, 0, 1, -1],
                     [0, 0, 1, -1, 1, 1]], dtype=np.int64)
 XI_D4S8 = np.hstack([2 * np.eye(4, dtype=np.int64), HAD4])
+# the paper's D4 spline (Sec. 5.2): the 8 directions (+-1, +-1, +-1, 1)
+XI_D4 = np.array([[1, 1, 1, 1, -1, -1, -1, -1],
+                  [1, 1, -1, -1, 1, 1, -1, -1],
+                  [1, -1, 1, -1, 1, -1, 1, -1],
+                  [1, 1, 1, 1, 1, 1, 1, 1]], dtype=np.int64)
+# D4 = 2 Z^4 + the 8 shifts with an even coordinate sum, ordered by sum l_a 2^a
+D4_SHIFTS = ((0, 0, 0, 0), (1, 1, 0, 0), (1, 0, 1, 0), (0, 1, 1, 0), (1, 0, 0, 1), (0, 1, 0, 1), (0, 0, 1, 1),
+             (1, 1, 1, 1))
 
 
 @dataclass(frozen=True)
@@ -90,6 +98,10 @@ CONFIGS = {
     "c5": Config("c5", "D4* 2x48^4, 8-direction box spline, 2^22 queries, forward + backward",
                  L_D4S, XI_D4S8, 2, (_z(4), (1, 1, 1, 1)), (48, 48, 48, 48), 1 << 22, 4.0, 91.0,
                  "field", passes="mse", lookups=60),
+    # the paper's own 4-D experiment (Sec. 5.2): 8 cosets, 240 lookups per query
+    "d4": Config("d4", "D4 8x24^4, 8-direction box spline of Sec. 5.2, FP32, 2^22 queries, forward",
+                 L_D4, XI_D4, 2, D4_SHIFTS, (24, 24, 24, 24), 1 << 22, 5.0, 42.0,
+                 "field", lookups=240),
 }
 
 
