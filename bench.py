@@ -5,7 +5,7 @@ coefficient volume (smooth random field + noise) and 2^24 uniform random
 FP32 queries, forward.  One step = one evaluation of all queries with the
 inputs resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c5|c1] [--dtype f32|bf16|f16]
+    python bench.py [--steps K] [--warmup W] [--config c2|c3|c4|c5|c1|d4] [--dtype f32|bf16|f16]
                     [--no-cpu] [--no-extra] [--order sorted|given] [--gpus 1]
 
 Besides the timed steps it reports the same step in the given query order,
@@ -33,6 +33,7 @@ WORKLOADS = {
     "c3": "BCC 2x192^3, quartic 7-direction box spline, 1024x1024 rays x 512 steps, forward + grad",
     "c4": "FCC 4x128^3 FP32, 6-direction box spline, 2^22 queries, MSE forward + backward",
     "c5": "D4* 2x48^4 FP32, 8-direction box spline, 2^22 queries, MSE forward + backward",
+    "d4": "D4 8x24^4 FP32, the 8-direction box spline of Sec. 5.2 (240 lookups), 2^22 queries, forward",
 }
 
 

@@ -19,7 +19,7 @@ namespace {
 
 using namespace lsp;
 
-enum SpecId { kBccLinear = 0, kCcZp, kBccQuartic, kFcc6, kD4s8, kNumSpecs };
+enum SpecId { kBccLinear = 0, kCcZp, kBccQuartic, kFcc6, kD4s8, kD48, kNumSpecs };
 
 struct SpecDesc {
   const char* name;
@@ -47,7 +47,7 @@ const std::vector<SpecDesc>& specs() {
   static const std::vector<SpecDesc> all = {
       describe<SplineBccLinear>("bcc_linear"), describe<SplineCcZp>("cc_zp"),
       describe<SplineBccQuartic>("bcc_quartic"), describe<SplineFcc6>("fcc_6dir"),
-      describe<SplineD4s8>("d4s_8dir")};
+      describe<SplineD4s8>("d4s_8dir"), describe<SplineD48>("d4_8dir")};
   return all;
 }
 
@@ -346,7 +346,17 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   }
   const Bin bn = make_bin<SP>(v, n);
   const BinGeom& gm = bn.g;
-  if (bn.lds_adj_g > kLdsMax) return LSP_ERR_UNSUPPORTED;
+  if (bn.lds_adj_g > kLdsMax) {
+    // a unit's region does not fit in LDS (large 4-D bricks): scatter-add
+    // with global atomics in the given order
+    if (grad_x)
+      hipLaunchKernelGGL((k_adjoint<SP, CT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, gv, x, g,
+                         static_cast<long long>(n), nullptr, grad_x);
+    else
+      hipLaunchKernelGGL((k_adjoint<SP, CT, false, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, gv, x, g,
+                         static_cast<long long>(n), nullptr, grad_x);
+    return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+  }
   const char* base = static_cast<const char*>(ws);
   const unsigned* start = reinterpret_cast<const unsigned*>(base + bn.off_start);
   const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
@@ -437,6 +447,7 @@ lsp_status rays_spec(const lsp_vol_s* v, const RayParams& rp, int64_t ray0, int6
     case kBccQuartic: return FN<SplineBccQuartic>(__VA_ARGS__); \
     case kFcc6: return FN<SplineFcc6>(__VA_ARGS__);           \
     case kD4s8: return FN<SplineD4s8>(__VA_ARGS__);           \
+    case kD48: return FN<SplineD48>(__VA_ARGS__);             \
   }                                                        \
   return LSP_ERR_UNSUPPORTED;
 

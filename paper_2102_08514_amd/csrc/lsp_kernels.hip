@@ -31,6 +31,7 @@ namespace lsp {
 #include "generated/bcc_quartic.inc"
 #include "generated/fcc_6dir.inc"
 #include "generated/d4s_8dir.inc"
+#include "generated/d4_8dir.inc"
 
 constexpr int kMaxCosets = 8;
 constexpr int kMaxDim = 4;

@@ -1,0 +1,64 @@
+"""Sec. 5.2's approximation study on the GPU path (FP64 coefficients): a
+Gaussian (sigma 0.125) is sampled on h D4, prefiltered (7/3 at the site,
+-1/18 at its 24 nearest neighbours) and reconstructed with the 8-direction
+box spline; the Monte-Carlo L2 error over [-0.5, 0.5]^4 (10,000 points) must
+fall by about 16 per halving of h once h is well below sigma (fourth order).
+The coarse levels are checked against the FP64 oracle as well."""
+
+import numpy as np
+import pytest
+
+from oracle import ConvolutionSumOracle
+from workloads import configs as W
+from workloads.d4 import gaussian, prefilter_samples, study_grid
+
+pytestmark = pytest.mark.gpu
+
+CFG = W.get("d4")
+LEVELS = (1 / 16, 1 / 32, 1 / 64, 1 / 128)
+
+
+def _level(lsp, torch, h, Xw):
+    """GPU reconstruction at the MC points and the Gaussian at the same
+    (float32-rounded) points; also returns the host arrays when small."""
+    o, N = study_grid(h, CFG)
+    dev = torch.device("cuda")
+    ax = torch.arange(N, dtype=torch.float64, device=dev)
+    grid = torch.stack(torch.meshgrid(ax, ax, ax, ax, indexing="ij"), dim=-1)   # [i3, i2, i1, i0, 4]
+    arrays = []
+    for k in range(CFG.M):
+        # coordinate a of coset k's element (i3, i2, i1, i0) is 2 (i_a - o) + l_k[a]
+        P = torch.stack([2.0 * (grid[..., 3 - a] - o) + CFG.shifts[k][a] for a in range(4)], dim=-1)
+        arrays.append(prefilter_samples(gaussian, P, h).contiguous())
+        del P
+    del grid
+    sp = lsp.LatticeSpline(CFG.L, CFG.Xi)
+    vol = sp.bind(arrays)
+    U = (Xw / h + 2 * o).astype(np.float32)
+    f = sp.eval(vol, torch.from_numpy(U).cuda()).cpu().numpy()
+    truth = gaussian((U.astype(np.float64) - 2 * o) * h)
+    host = [a.cpu().numpy() for a in arrays] if N <= 16 else None
+    return f, truth, U, host
+
+
+def test_d4_fourth_order_convergence(lsp):
+    import torch
+    rng = np.random.default_rng(52)
+    Xw = rng.uniform(-0.5, 0.5, (10000, 4))
+    errs = []
+    for h in LEVELS:
+        f, truth, U, host = _level(lsp, torch, h, Xw)
+        err = float(np.sqrt(np.mean((f - truth) ** 2)))
+        errs.append(err)
+        print(f"h = 1/{round(1 / h)}: L2 error {err:.3e}", flush=True)
+        if host is not None:
+            # the GPU reconstruction is the oracle's, to FP64 rounding
+            o = ConvolutionSumOracle(CFG.L, CFG.Xi)
+            want = o.eval(host, U[:64].astype(np.float64))
+            assert np.max(np.abs(f[:64] - want)) <= 1e-11
+        torch.cuda.empty_cache()
+    ratios = [a / b for a, b in zip(errs, errs[1:])]
+    print("ratios", ratios, flush=True)
+    assert all(r > 1.0 for r in ratios)
+    # fourth order: error / 16 per halving (log2 ratio 4) in the asymptotic range
+    assert 3.5 <= np.log2(ratios[-1]) <= 4.5

@@ -13,7 +13,7 @@ import pytest
 from paper_2102_08514_amd.gen.interp import orbit_of
 from paper_2102_08514_amd.gen.tables import GENERATED, load
 
-NAMES = ["bcc_linear", "cc_zp", "bcc_quartic", "fcc_6dir", "d4s_8dir"]
+NAMES = ["bcc_linear", "cc_zp", "bcc_quartic", "fcc_6dir", "d4s_8dir", "d4_8dir"]
 
 
 def _functions(text):
@@ -120,7 +120,7 @@ def test_emitted_code_matches_tables(name):
             assert abs(wv - float(P(tuple(Fraction(float(v)) for v in u)))) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["fcc_6dir", "d4s_8dir"])
+@pytest.mark.parametrize("name", ["fcc_6dir", "d4s_8dir", "d4_8dir"])
 def test_emitted_subregion_selector(name):
     t = load(name)
     text = open(f"{GENERATED}/{name}.inc").read()

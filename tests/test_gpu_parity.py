@@ -18,8 +18,9 @@ from workloads import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 10, 10), "c5": (7, 7, 7, 7)}
-NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601}
+SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 10, 10), "c5": (7, 7, 7, 7),
+         "d4": (8, 8, 8, 8)}
+NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601, "d4": 401}
 
 
 def _torch():
@@ -55,7 +56,7 @@ def normwise(a, b, coeffs):
     return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)))) / scale
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"])
 def test_forward_fp32(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name)
@@ -71,7 +72,7 @@ def test_forward_fp32(lsp, name):
     assert normwise(f, want, coeffs) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"])
 def test_forward_fp64_check(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=1)
@@ -101,7 +102,7 @@ def test_forward_low_precision_storage(lsp, name, dt):
     assert normwise(f, o.eval(rounded, X.astype(np.float64)), coeffs) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c5", "d4"])
 def test_gradient(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=3)
@@ -115,7 +116,7 @@ def test_gradient(lsp, name):
     assert err <= 1e-4
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5", "d4"])
 def test_adjoint(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=4)
@@ -135,7 +136,7 @@ def test_adjoint(lsp, name):
         assert normwise(gx.cpu().numpy(), g[:, None] * gw, coeffs) <= 1e-4 * max(1.0, float(np.max(np.abs(g))))
 
 
-@pytest.mark.parametrize("name", ["c4", "c5"])
+@pytest.mark.parametrize("name", ["c4", "c5", "d4"])
 def test_mse_head(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=6)
@@ -267,7 +268,7 @@ def test_full_size_sampled_c2(lsp):
     assert np.all(np.isfinite(f))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"])
 def test_scheduled_order(lsp, name):
     """The counting-sort schedule changes only the evaluation order: results
     equal the given-order ones (bitwise for one sub-region; up to the order of

@@ -18,7 +18,7 @@ from paper_2102_08514_amd.gen.specs import SPECS
 from paper_2102_08514_amd.gen.tables import GENERATED, load
 from workloads import configs as W
 
-NAMES = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir"}
+NAMES = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir", "d4": "d4_8dir"}
 
 
 @pytest.mark.parametrize("cfg_name", list(NAMES))
