@@ -31,6 +31,7 @@
 // are grouped by sub-region, so a wave runs one polynomial set instead of
 // predicating all of them (Sec. 4.3).  Per-coset results go to partial
 // buffers and are summed by a combine kernel.
+#pragma once
 
 namespace lsp {
 
@@ -157,6 +158,7 @@ __global__ void __launch_bounds__(1024) k_bin_hist(Vol vol, BinGeom g, const flo
 }
 
 // 2. per key: exclusive running sum over tiles (in place) and the key total
+template <int = 0>
 __global__ void __launch_bounds__(256) k_bin_colscan(unsigned* __restrict__ hist, int tiles, unsigned nkeys,
                                                      unsigned* __restrict__ tot) {
   const unsigned key = blockIdx.x * blockDim.x + threadIdx.x;
@@ -761,6 +763,7 @@ __device__ __forceinline__ unsigned block_max_u32(unsigned v, unsigned* red) {
   return v;
 }
 
+template <int = 0>
 __global__ void __launch_bounds__(256) k_absmax_partial(const float* __restrict__ gout, long long n,
                                                         unsigned* __restrict__ partial) {
   __shared__ unsigned red[4];
@@ -772,6 +775,7 @@ __global__ void __launch_bounds__(256) k_absmax_partial(const float* __restrict_
   if (threadIdx.x == 0) partial[blockIdx.x] = m;
 }
 
+template <int = 0>
 __global__ void __launch_bounds__(1024) k_absmax_final(const unsigned* __restrict__ partial, int parts,
                                                        unsigned* __restrict__ out) {
   __shared__ unsigned red[16];

@@ -18,6 +18,7 @@
 // The gathers read the coefficient arrays directly through the cache
 // hierarchy; the per-lane work is VALU FMAs.  No MFMA: the weights differ per
 // query, there is no shared dense operand.
+#pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,6 +33,11 @@ namespace lsp {
 #include "generated/fcc_6dir.inc"
 #include "generated/d4s_8dir.inc"
 #include "generated/d4_8dir.inc"
+#include "generated/cc_tp2.inc"
+#include "generated/cc_tp3.inc"
+#include "generated/cc_tp4.inc"
+#include "generated/cc_linear_rd.inc"
+#include "generated/bcc_quintic_rd.inc"
 
 constexpr int kMaxCosets = 8;
 constexpr int kMaxDim = 4;
@@ -444,19 +450,6 @@ __device__ __forceinline__ void mse_reduce(float r2, double inv_n, double* loss)
   }
 }
 
-__global__ void __launch_bounds__(256) k_mse_head(const float* __restrict__ f, const float* __restrict__ y,
-                                                  long long n, float inv_n, float* __restrict__ dldf,
-                                                  double* __restrict__ loss) {
-  float r2 = 0.f;
-  for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
-       q += static_cast<long long>(gridDim.x) * blockDim.x) {
-    const float r = f[q] - y[q];
-    dldf[q] = 2.f * r * inv_n;
-    r2 += r * r;
-  }
-  mse_reduce(r2, static_cast<double>(inv_n), loss);
-}
-
 // forward fused with the MSE head (whole queries per lane); GRAD also writes
 // dL/dx = dL/df * grad f
 template <class SP, class CT, bool GRAD>
@@ -525,12 +518,6 @@ __global__ void __launch_bounds__(256) k_adjoint(Vol vol, GradVol gvol, const fl
 
 // ----------------------------------------------------------------------------
 // small utility kernels
-__global__ void __launch_bounds__(256) k_fill_u32(unsigned* __restrict__ p, long long n, unsigned v) {
-  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += static_cast<long long>(gridDim.x) * blockDim.x)
-    p[i] = v;
-}
-
 template <class T>
 __global__ void __launch_bounds__(256) k_fill_zero(T* __restrict__ p, long long n) {
   for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -559,6 +546,7 @@ __device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned* l
   return incl - v;
 }
 
+template <int = 0>
 __global__ void __launch_bounds__(256) k_scan_blocks(const unsigned* __restrict__ in, unsigned* __restrict__ out,
                                                      unsigned* __restrict__ partial, unsigned n) {
   __shared__ unsigned lds[256];
@@ -577,6 +565,7 @@ __global__ void __launch_bounds__(256) k_scan_blocks(const unsigned* __restrict_
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
+template <int = 0>
 __global__ void __launch_bounds__(256) k_scan_top(unsigned* __restrict__ partial, unsigned nblocks) {
   __shared__ unsigned lds[256];
   const unsigned base = threadIdx.x * 4;
@@ -592,6 +581,7 @@ __global__ void __launch_bounds__(256) k_scan_top(unsigned* __restrict__ partial
   }
 }
 
+template <int = 0>
 __global__ void __launch_bounds__(256) k_scan_add(unsigned* __restrict__ out, const unsigned* __restrict__ partial,
                                                   unsigned n) {
   const unsigned add = partial[blockIdx.x];

@@ -32,4 +32,10 @@ SPECS = {
     "fcc_6dir": ("SplineFcc6", L_FCC, [[1, -1, 1, 1, 0, 0], [1, 1, 0, 0, 1, -1], [0, 0, 1, -1, 1, 1]]),
     "d4s_8dir": ("SplineD4s8", L_D4S, _hcat(_scale(I4, 2), [list(r) for r in zip(*HAD4_COLS)])),
     "d4_8dir": ("SplineD48", L_D4, XI_D4),
+    # the remaining box-spline rows of Table 1
+    "cc_tp2": ("SplineCcTp2", L_CC, _hcat(I3, I3)),
+    "cc_tp3": ("SplineCcTp3", L_CC, _hcat(I3, I3, I3)),
+    "cc_tp4": ("SplineCcTp4", L_CC, _hcat(I3, I3, I3, I3)),
+    "cc_linear_rd": ("SplineCcLinearRd", L_CC, BCC_DIAG),
+    "bcc_quintic_rd": ("SplineBccQuinticRd", L_BCC, _hcat(BCC_DIAG, BCC_DIAG)),
 }

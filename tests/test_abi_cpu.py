@@ -57,7 +57,7 @@ def test_plan_accepts_equivalent_inputs():
 def test_plan_errors():
     L = _lib()
     with pytest.raises(L.LspError) as e:
-        L.lsp_plan_create(W.L_CC, W.XI_BCC_LINEAR)           # valid but no tables
+        L.lsp_plan_create(W.L_CC, [[1, 0, 0, 1], [0, 1, 0, 1], [0, 0, 1, 1]])   # valid but no tables
     assert e.value.status == -3
     with pytest.raises(L.LspError) as e:
         L.lsp_plan_create(W.L_FCC, W.XI_ZP)                  # e1 is not an FCC vector

@@ -13,7 +13,8 @@ import pytest
 from paper_2102_08514_amd.gen.interp import orbit_of
 from paper_2102_08514_amd.gen.tables import GENERATED, load
 
-NAMES = ["bcc_linear", "cc_zp", "bcc_quartic", "fcc_6dir", "d4s_8dir", "d4_8dir"]
+NAMES = ["bcc_linear", "cc_zp", "bcc_quartic", "fcc_6dir", "d4s_8dir", "d4_8dir", "cc_tp2", "cc_tp3", "cc_tp4",
+         "cc_linear_rd", "bcc_quintic_rd"]
 
 
 def _functions(text):

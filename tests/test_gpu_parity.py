@@ -19,8 +19,12 @@ from workloads import inputs as I
 pytestmark = pytest.mark.gpu
 
 SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 10, 10), "c5": (7, 7, 7, 7),
-         "d4": (8, 8, 8, 8)}
-NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601, "d4": 401}
+         "d4": (8, 8, 8, 8), "cc_tp2": (20, 20, 20), "cc_tp3": (20, 20, 20), "cc_tp4": (20, 20, 20),
+         "cc_linear_rd": (20, 20, 20), "bcc_quintic_rd": (12, 12, 12)}
+NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601, "d4": 401, "cc_tp2": 1301, "cc_tp3": 1301,
+      "cc_tp4": 96, "cc_linear_rd": 1301, "bcc_quintic_rd": 1301}   # cc_tp4: 12 directions make the oracle slow
+TABLE1 = ["cc_tp2", "cc_tp3", "cc_tp4", "cc_linear_rd", "bcc_quintic_rd"]
+C0_SPLINES = ("c1", "cc_tp2", "cc_linear_rd")   # linear pieces
 
 
 def _torch():
@@ -56,7 +60,7 @@ def normwise(a, b, coeffs):
     return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)))) / scale
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"] + TABLE1)
 def test_forward_fp32(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name)
@@ -72,7 +76,7 @@ def test_forward_fp32(lsp, name):
     assert normwise(f, want, coeffs) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"] + TABLE1)
 def test_forward_fp64_check(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=1)
@@ -102,7 +106,7 @@ def test_forward_low_precision_storage(lsp, name, dt):
     assert normwise(f, o.eval(rounded, X.astype(np.float64)), coeffs) <= 1e-5
 
 
-@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c5", "d4"])
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c5", "d4", "cc_tp3", "cc_tp4", "bcc_quintic_rd"])
 def test_gradient(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=3)
@@ -116,7 +120,7 @@ def test_gradient(lsp, name):
     assert err <= 1e-4
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5", "d4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5", "d4"] + TABLE1)
 def test_adjoint(lsp, name):
     torch = _torch()
     cfg, coeffs, X = small_case(name, seed=4)
@@ -131,7 +135,7 @@ def test_adjoint(lsp, name):
     gc, gx = sp.adjoint(vol, torch.from_numpy(X).cuda(), torch.from_numpy(g).cuda(), grad_x=True)
     for a, b in zip(gc, want):
         assert float(np.max(np.abs(a.cpu().numpy() - b))) <= 1e-5 * bound
-    if name != "c1":   # c1 is only C0: its gradient is two-valued on the mesh planes
+    if name not in C0_SPLINES:   # only C0: the gradient is two-valued on the mesh planes
         _, gw = o.eval(coeffs, X.astype(np.float64), want_grad=True)
         assert normwise(gx.cpu().numpy(), g[:, None] * gw, coeffs) <= 1e-4 * max(1.0, float(np.max(np.abs(g))))
 
@@ -268,13 +272,13 @@ def test_full_size_sampled_c2(lsp):
     assert np.all(np.isfinite(f))
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"] + TABLE1)
 def test_scheduled_order(lsp, name):
     """The counting-sort schedule changes only the evaluation order: results
     equal the given-order ones (bitwise for one sub-region; up to the order of
     the per-coset float additions otherwise) and the oracle."""
     torch = _torch()
-    cfg, coeffs, X = small_case(name, n=2503, seed=12)
+    cfg, coeffs, X = small_case(name, n=2503 if NQ[name] >= 1301 else NQ[name], seed=12)
     o = ConvolutionSumOracle(cfg.L, cfg.Xi)
     sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
     vol = sp.bind(to_dev(coeffs, torch.float32))

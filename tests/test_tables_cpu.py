@@ -18,7 +18,9 @@ from paper_2102_08514_amd.gen.specs import SPECS
 from paper_2102_08514_amd.gen.tables import GENERATED, load
 from workloads import configs as W
 
-NAMES = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir", "d4": "d4_8dir"}
+NAMES = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir", "d4": "d4_8dir",
+         "cc_tp2": "cc_tp2", "cc_tp3": "cc_tp3", "cc_tp4": "cc_tp4", "cc_linear_rd": "cc_linear_rd",
+         "bcc_quintic_rd": "bcc_quintic_rd"}
 
 
 @pytest.mark.parametrize("cfg_name", list(NAMES))

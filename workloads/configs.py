@@ -102,6 +102,18 @@ CONFIGS = {
     "d4": Config("d4", "D4 8x24^4, 8-direction box spline of Sec. 5.2, FP32, 2^22 queries, forward",
                  L_D4, XI_D4, 2, D4_SHIFTS, (24, 24, 24, 24), 1 << 22, 5.0, 42.0,
                  "field", lookups=240),
+    # the remaining box-spline rows of Table 1 (parity cases)
+    "cc_tp2": Config("cc_tp2", "Z^3 64^3, [I3 I3] (trilinear; Table 1 CC Voronoi 1)", L_CC, np.hstack([I3] * 2), 1,
+                     (_z(3),), (64, 64, 64), 1 << 20, 1.0, 62.0, "uniform", lookups=8),
+    "cc_tp3": Config("cc_tp3", "Z^3 64^3, [I3 I3 I3] (triquadratic; Table 1 CC Voronoi 2)", L_CC,
+                     np.hstack([I3] * 3), 1, (_z(3),), (64, 64, 64), 1 << 20, 1.5, 61.5, "uniform", lookups=27),
+    "cc_tp4": Config("cc_tp4", "Z^3 64^3, [I3 I3 I3 I3] (tricubic; Table 1 CC Voronoi 3)", L_CC,
+                     np.hstack([I3] * 4), 1, (_z(3),), (64, 64, 64), 1 << 20, 2.0, 61.0, "uniform", lookups=64),
+    "cc_linear_rd": Config("cc_linear_rd", "Z^3 64^3, the 4 BCC diagonals (Table 1 CC linear rhombic dodecahedron)",
+                           L_CC, BCC_DIAG, 1, (_z(3),), (64, 64, 64), 1 << 20, 2.0, 61.0, "uniform", lookups=16),
+    "bcc_quintic_rd": Config("bcc_quintic_rd", "BCC 2x32^3, the BCC diagonals twice (Table 1 quintic rhombic "
+                             "dodecahedron)", L_BCC, np.hstack([BCC_DIAG] * 2), 2, (_z(3), (1, 1, 1)), (32, 32, 32),
+                             1 << 20, 5.0, 58.0, "uniform", lookups=32),
 }
 
 

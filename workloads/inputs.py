@@ -16,8 +16,16 @@ import numpy as np
 from .configs import CONFIGS
 
 
+def _seed_index(name):
+    """c1..c5 keep their number; the other workloads follow in table order."""
+    if name[0] == "c" and name[1:].isdigit():
+        return int(name[1:])
+    others = [n for n in CONFIGS if not (n[0] == "c" and n[1:].isdigit())]
+    return 6 + others.index(name)
+
+
 def _rng(cfg, stream):
-    return np.random.Generator(np.random.PCG64(1000 * int(cfg.name[1:]) + stream))
+    return np.random.Generator(np.random.PCG64(1000 * _seed_index(cfg.name) + stream))
 
 
 def field_params(cfg, stream=3, count=8):
