@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the context legs (given order, cold cache, copy bandwidth)")
+    ap.add_argument("--render", action="store_true",
+                    help="c3: time the volume renderer (transfer function, shading, compositing) instead of the "
+                         "plain ray sums")
     ap.add_argument("--order", default="sorted", choices=["sorted", "given"],
                     help="evaluate in the library's scheduled order (timed) or in the given order")
     args = ap.parse_args()
@@ -212,10 +215,20 @@ def main():
         cf, Af = c.astype(np.float32), A.astype(np.float32)
         phases = ["rays"]
 
-        def step(marks, sched=None):
-            sp.rays(vol, cf, Af, W_, H_, S_)
+        if args.render:
+            # mostly transparent transfer function: every ray crosses the whole volume
+            tfv = torch.tensor([[0.1, 0.2, 0.9, 0.0], [0.2, 0.8, 0.3, 0.004], [0.9, 0.7, 0.1, 0.008],
+                                [1.0, 0.2, 0.1, 0.012]], device="cuda")
+            phases = ["render"]
+
+            def step(marks, sched=None):
+                sp.render(vol, cf, Af, W_, H_, S_, tfv, -0.5, 0.5, alpha_stop=2.0)
+            kernels = "k_render"
+        else:
+            def step(marks, sched=None):
+                sp.rays(vol, cf, Af, W_, H_, S_)
+            kernels = "k_rays"
         bytes_per = Lq * bytes_c + 16.0 / S_                     # coefficients + per-ray output
-        kernels = "k_rays"
     else:
         X = I.queries(cfg)
         n = len(X)
@@ -307,7 +320,7 @@ def main():
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "spline": info["name"],
                    "n_samples": n, "lookups_per_sample": Lq, "volume_dims": list(cfg.dims),
                    "n_cosets": cfg.M, "passes": cfg.passes,
-                   "order": "rays" if X is None else args.order},
+                   "order": ("render" if args.render else "rays") if X is None else args.order},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],

@@ -133,6 +133,33 @@ lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const fl
 lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
                          int32_t steps, int64_t ray0, int64_t nrays, float* out, float* samples, void* stream);
 
+/* Volume rendering (3-D only; the application the paper measures in Sec. 5.1:
+ * volumetric, not iso-surface, with a mostly transparent transfer function so
+ * that rays cross the whole volume).  Rays and samples as in lsp_eval_rays.
+ * Each sample's f selects an RGBA value from the transfer function tf
+ * (device, tf_len float4 entries, 16-byte aligned; entry 0 at f0, entry
+ * tf_len - 1 at f1, linear in between, clamped outside); its colour is shaded
+ * with grad f as the normal under a light along the ray direction d:
+ *   shade = ambient + diffuse |grad f . d| / |grad f|
+ * (ambient + diffuse where |grad f| <= grad_eps), and the samples are
+ * composited front to back from sample 0:
+ *   C += (1 - A) alpha shade rgb,   A += (1 - A) alpha,
+ * stopping once A >= alpha_stop (a value above 1 marches every step).
+ * Writes (C, A) per ray to rgba (device, nrays x 4 float32, 16-byte aligned).
+ * Errors: LSP_ERR_INVALID for bad geometry, tf_len < 2, f1 <= f0 or
+ * grad_eps < 0; LSP_ERR_DTYPE for LSP_F64 volumes. */
+typedef struct lsp_render_params {
+  float f0, f1;             /* transfer-function domain */
+  float ambient, diffuse;   /* shading weights */
+  float grad_eps;           /* below this gradient norm the sample is unshaded */
+  float alpha_stop;         /* early ray termination threshold */
+  int32_t tf_len;           /* transfer-function entries (>= 2) */
+} lsp_render_params;
+
+lsp_status lsp_render(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
+                      int32_t steps, int64_t ray0, int64_t nrays, const float* tf,
+                      const lsp_render_params* params, float* rgba, void* stream);
+
 /* Query schedule (evaluation order).  Random queries gather from random
  * places of the volume; ordering the work items so that neighbouring lanes
  * read neighbouring coefficients makes the stencil gathers hit the caches

@@ -17,7 +17,7 @@ EXPORTS = (
     "lsp_plan_create", "lsp_plan_info", "lsp_plan_destroy", "lsp_vol_bind", "lsp_vol_release",
     "lsp_eval", "lsp_eval_mse", "lsp_eval_adjoint", "lsp_eval_rays", "lsp_status_string",
     "lsp_schedule_size", "lsp_schedule", "lsp_eval_scheduled", "lsp_eval_mse_scheduled",
-    "lsp_eval_adjoint_scheduled",
+    "lsp_eval_adjoint_scheduled", "lsp_render",
 )
 
 
@@ -29,6 +29,13 @@ class LspInfo(ctypes.Structure):
         ("stencil", ctypes.c_int32 * 16), ("lookups", ctypes.c_int32), ("n_monomials", ctypes.c_int32),
         ("nnz", ctypes.c_int32 * 16), ("offset_min", ctypes.c_int32), ("offset_max", ctypes.c_int32),
         ("name", ctypes.c_char * 32),
+    ]
+
+
+class LspRenderParams(ctypes.Structure):
+    _fields_ = [
+        ("f0", ctypes.c_float), ("f1", ctypes.c_float), ("ambient", ctypes.c_float), ("diffuse", ctypes.c_float),
+        ("grad_eps", ctypes.c_float), ("alpha_stop", ctypes.c_float), ("tf_len", ctypes.c_int32),
     ]
 
 
@@ -65,6 +72,8 @@ def lib():
         L.lsp_eval_scheduled.argtypes = [vp, vp, vp, i64, vp, sz, vp, vp, vp]
         L.lsp_eval_mse_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, vp, vp, vp, vp, vp]
         L.lsp_eval_adjoint_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, P(vp), vp, vp]
+        L.lsp_render.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), i32, i32, i32, i64, i64, vp,
+                                 P(LspRenderParams), vp, vp]
         L.lsp_status_string.argtypes = [i32]
         L.lsp_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -175,3 +184,13 @@ def lsp_eval_adjoint_scheduled(plan, vol, x_ptr, g_ptr, n, ws_ptr, ws_bytes, gra
     arr = (ctypes.c_void_p * len(grad_c_ptrs))(*[int(p) for p in grad_c_ptrs])
     check(lib().lsp_eval_adjoint_scheduled(plan, vol, x_ptr, g_ptr, int(n), ws_ptr, int(ws_bytes), arr, grad_x_ptr,
                                            stream), "lsp_eval_adjoint_scheduled")
+
+
+def lsp_render(plan, vol, c, A, W, H, steps, ray0, nrays, tf_ptr, params, rgba_ptr, stream):
+    """params: dict with f0, f1, ambient, diffuse, grad_eps, alpha_stop, tf_len."""
+    cc = (ctypes.c_float * 3)(*[float(v) for v in c])
+    AA = (ctypes.c_float * 9)(*[float(v) for v in A])
+    p = LspRenderParams(**{k: params[k] for k in ("f0", "f1", "ambient", "diffuse", "grad_eps", "alpha_stop",
+                                                  "tf_len")})
+    check(lib().lsp_render(plan, vol, cc, AA, int(W), int(H), int(steps), int(ray0), int(nrays), tf_ptr,
+                           ctypes.byref(p), rgba_ptr, stream), "lsp_render")

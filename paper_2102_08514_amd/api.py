@@ -161,3 +161,19 @@ class LatticeSpline:
         L.lsp_eval_rays(self.plan, vol.handle, list(centre), [float(v) for row in A for v in row], W, H, steps,
                         ray0, nrays, out.data_ptr(), _ptr(smp), _stream())
         return (out, smp) if samples else out
+
+    def render(self, vol, centre, A, W, H, steps, tf, f0, f1, ambient=0.3, diffuse=0.7, grad_eps=1e-6,
+               alpha_stop=2.0, ray0=0, nrays=None):
+        """Volume rendering of rays [ray0, ray0 + nrays) (see lsp_render): tf is a
+        (T, 4) float32 RGBA tensor on the GPU spanning f in [f0, f1]; returns
+        (nrays, 4) float32 (premultiplied colour, opacity)."""
+        _require_device(tf)
+        if tf.dtype != torch.float32 or tf.dim() != 2 or tf.shape[1] != 4:
+            raise ValueError("tf must be a T x 4 float32 tensor")
+        nrays = W * H - ray0 if nrays is None else nrays
+        out = torch.empty(nrays, 4, device=tf.device, dtype=torch.float32)
+        params = {"f0": float(f0), "f1": float(f1), "ambient": float(ambient), "diffuse": float(diffuse),
+                  "grad_eps": float(grad_eps), "alpha_stop": float(alpha_stop), "tf_len": int(tf.shape[0])}
+        L.lsp_render(self.plan, vol.handle, list(centre), [float(v) for row in A for v in row], W, H, steps, ray0,
+                     nrays, tf.data_ptr(), params, out.data_ptr(), _stream())
+        return out

@@ -352,6 +352,32 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
   LSP_DISPATCH(plan->spec, rays_spec, vol, rp, ray0, nrays, out, samples, s)
 }
 
+lsp_status lsp_render(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
+                      int32_t steps, int64_t ray0, int64_t nrays, const float* tf,
+                      const lsp_render_params* params, float* rgba, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (!c || !A || !params) return LSP_ERR_NULL;
+  if (W <= 0 || H <= 0 || (W & 7) || (H & 7) || steps <= 0 || ray0 < 0 || nrays < 0 ||
+      ray0 + nrays > static_cast<int64_t>(W) * H)
+    return LSP_ERR_INVALID;
+  const lsp_render_params& p = *params;
+  if (p.tf_len < 2 || !(p.f1 > p.f0) || !(p.grad_eps >= 0.f)) return LSP_ERR_INVALID;
+  if (nrays == 0) return LSP_OK;
+  if (!tf || !rgba) return LSP_ERR_NULL;
+  if (reinterpret_cast<uintptr_t>(tf) & 15 || reinterpret_cast<uintptr_t>(rgba) & 15) return LSP_ERR_INVALID;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  RayParams rp{};
+  for (int a = 0; a < 3; ++a) rp.c[a] = c[a];
+  for (int a = 0; a < 9; ++a) rp.A[a] = A[a];
+  rp.W = W; rp.H = H; rp.steps = steps;
+  RenderParams rd{};
+  rd.f0 = p.f0; rd.f1 = p.f1; rd.ambient = p.ambient; rd.diffuse = p.diffuse; rd.grad_eps = p.grad_eps;
+  rd.alpha_stop = p.alpha_stop; rd.tf_len = p.tf_len;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, render_spec, vol, rp, rd, tf, ray0, nrays, rgba, s)
+}
+
 static lsp_status check_ws(lsp_plan plan, lsp_vol vol, int64_t n, const void* ws, size_t ws_bytes) {
   if (!ws) return LSP_ERR_NULL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return LSP_ERR_INVALID;

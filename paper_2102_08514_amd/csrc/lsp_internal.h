@@ -41,4 +41,8 @@ template <class SP>
 lsp_status rays_spec(const lsp_vol_s* v, const lsp::RayParams& rp, int64_t ray0, int64_t nrays, float* out,
                      float* samples, hipStream_t st);
 
+template <class SP>
+lsp_status render_spec(const lsp_vol_s* v, const lsp::RayParams& rp, const lsp::RenderParams& rd, const float* tf,
+                       int64_t ray0, int64_t nrays, float* out, hipStream_t st);
+
 }  // namespace lsp_host

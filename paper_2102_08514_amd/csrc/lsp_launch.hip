@@ -327,6 +327,32 @@ lsp_status rays_spec(const lsp_vol_s* v, const RayParams& rp, int64_t ray0, int6
   }
 }
 
+template <class SP, class CT>
+lsp_status launch_render(const lsp_vol_s* v, const RayParams& rp, const RenderParams& rd, const float* tf,
+                         int64_t ray0, int64_t nrays, float* out, hipStream_t st) {
+  const int block = 256;
+  const long long grid = (nrays + block - 1) / block;
+  hipLaunchKernelGGL((k_render<SP, CT>), dim3(static_cast<unsigned>(grid)), dim3(block), 0, st, v->vol, rp, rd,
+                     reinterpret_cast<const float4*>(tf), static_cast<long long>(ray0),
+                     static_cast<long long>(nrays), reinterpret_cast<float4*>(out));
+  return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
+}
+
+template <class SP>
+lsp_status render_spec(const lsp_vol_s* v, const RayParams& rp, const RenderParams& rd, const float* tf,
+                       int64_t ray0, int64_t nrays, float* out, hipStream_t st) {
+  if constexpr (SP::S != 3) {
+    return LSP_ERR_UNSUPPORTED;
+  } else {
+    switch (v->dtype) {
+      case LSP_F32: return launch_render<SP, float>(v, rp, rd, tf, ray0, nrays, out, st);
+      case LSP_BF16: return launch_render<SP, bf16_t>(v, rp, rd, tf, ray0, nrays, out, st);
+      case LSP_F16: return launch_render<SP, f16_t>(v, rp, rd, tf, ray0, nrays, out, st);
+    }
+    return LSP_ERR_DTYPE;
+  }
+}
+
 }  // namespace lsp_host
 
 // explicit instantiation of every launcher of spline type SP
@@ -342,4 +368,6 @@ lsp_status rays_spec(const lsp_vol_s* v, const RayParams& rp, int64_t ray0, int6
   template lsp_status sched_spec<SP>(const lsp_vol_s*, const float*, int64_t, void*, hipStream_t);               \
   template lsp_status rays_spec<SP>(const lsp_vol_s*, const RayParams&, int64_t, int64_t, float*, float*,        \
                                     hipStream_t);                                                               \
+  template lsp_status render_spec<SP>(const lsp_vol_s*, const RayParams&, const RenderParams&, const float*,     \
+                                      int64_t, int64_t, float*, hipStream_t);                                   \
   }

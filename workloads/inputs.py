@@ -120,11 +120,12 @@ def ray_params(cfg, primary=True):
     return centre, R * a
 
 
-def ray_samples(cfg, pixels, steps, W=1024, H=1024, S=512, primary=True):
+def ray_samples(cfg, pixels, steps, W=1024, H=1024, S=512, primary=True, params=None):
     """World positions of the samples (pixel index u + W v, step j), computed
     in float32 exactly as the GPU ray generator does: p = c + A t with
-    t = 2(q + 1/2)/n - 1 per axis, each float32 operation rounded."""
-    c, A = ray_params(cfg, primary)
+    t = 2(q + 1/2)/n - 1 per axis, each float32 operation rounded.
+    params: (c, A) instead of the workload's own ray grid."""
+    c, A = ray_params(cfg, primary) if params is None else (np.asarray(params[0]), np.asarray(params[1]))
     c32 = c.astype(np.float32)
     A32 = A.astype(np.float32)
     pixels = np.asarray(pixels, dtype=np.int64)
