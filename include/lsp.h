@@ -185,8 +185,13 @@ lsp_status lsp_render(lsp_plan plan, lsp_vol vol, const float* c, const float* A
  * *_scheduled calls then evaluate the same x (same n) in that order; results
  * land at each query's own index, exactly as the unscheduled calls.
  * Errors: LSP_ERR_NULL, LSP_ERR_INVALID (workspace too small or misaligned,
- * n * cosets >= 2^32).  The adjoint's float additions into grad_c within a
- * unit happen in an unspecified order (LDS atomics). */
+ * n * cosets >= 2^32).  The scheduled adjoint sums each unit's terms in
+ * 64-bit fixed point (scale: a power of two from max |g|, terms resolved to
+ * 2^-49 max|g| or finer for units of up to 4096 items), so its result does
+ * not depend on the order of the additions; a non-finite g makes the
+ * affected grad_c entries NaN.  Items whose stencil leaves their unit's
+ * region (queries outside the stored volume), and volumes whose units do
+ * not fit in LDS, fall back to float atomics. */
 lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes);
 lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace, size_t ws_bytes,
                         void* stream);

@@ -337,3 +337,37 @@ def test_scheduled_full_size_sampled(lsp):
     lhs = float(torch.dot(f.double(), g.double()))
     rhs = float(sum(torch.sum(c.double() * a.double()) for c, a in zip(dev, gc)))
     assert abs(lhs - rhs) <= 1e-4 * (abs(lhs) + float(g.abs().sum()) * 1e-3)
+
+
+@pytest.mark.parametrize("name", ["c2", "c4", "c5"])
+def test_scheduled_adjoint_fixed_point_scaling(lsp, name):
+    """The scheduled adjoint accumulates in 64-bit fixed point with a power-of-
+    two scale taken from max |g|: scaling g by a power of two scales the
+    result exactly (the same integers are summed), for tiny and huge g; its
+    sums do not depend on the order of the additions (two runs agree
+    bitwise); a non-finite g turns the result into NaN."""
+    torch = _torch()
+    n = 1301 if cfg_s(name) == 3 else 601
+    cfg, coeffs, X = small_case(name, n=n, seed=21)
+    X = np.ascontiguousarray(X[: n // 2])      # interior queries: every item is accumulated in LDS
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    x = torch.from_numpy(X).cuda()
+    sch = sp.schedule(vol, x)
+    g = torch.from_numpy(np.random.default_rng(22).normal(size=len(X)).astype(np.float32)).cuda()
+    base, _ = sp.adjoint(vol, x, g, schedule=sch)
+    again, _ = sp.adjoint(vol, x, g, schedule=sch)
+    for a, b in zip(base, again):
+        assert torch.equal(a, b)
+    for e in (-60, 60):
+        scaled, _ = sp.adjoint(vol, x, torch.ldexp(g, torch.tensor(e, device="cuda")), schedule=sch)
+        for a, b in zip(base, scaled):
+            assert torch.equal(torch.ldexp(a, torch.tensor(e, device="cuda")), b)
+    gn = g.clone()
+    gn[7] = float("nan")
+    bad, _ = sp.adjoint(vol, x, gn, schedule=sch)
+    assert any(bool(torch.isnan(a).any()) for a in bad)
+
+
+def cfg_s(name):
+    return W.get(name).s
