@@ -187,7 +187,7 @@ lsp_status lsp_render(lsp_plan plan, lsp_vol vol, const float* c, const float* A
  * Errors: LSP_ERR_NULL, LSP_ERR_INVALID (workspace too small or misaligned,
  * n * cosets >= 2^32).  The scheduled adjoint sums each unit's terms in
  * 64-bit fixed point (scale: a power of two from max |g|, terms resolved to
- * 2^-49 max|g| or finer for units of up to 4096 items), so its result does
+ * 2^-49 max|g| or finer for units of fewer than 2048 items), so its result does
  * not depend on the order of the additions; a non-finite g makes the
  * affected grad_c entries NaN.  Items whose stencil leaves their unit's
  * region (queries outside the stored volume), and volumes whose units do
