@@ -245,19 +245,20 @@ def main():
             gx = torch.empty(n, s, device="cuda")
             phases = ["schedule", "forward", "backward"]
 
-            def step(marks, sched=use_sched):
+            def step(marks, sched=use_sched, want_f=False):
                 if sched:
                     Lb.lsp_schedule(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes, strm)
                 mark(marks, 0)
                 loss.zero_()
-                # forward: f, dL/df, L and dL/dx; backward: dL/dc (scatter-add into zeroed arrays)
+                # forward: L, dL/df and dL/dx (f itself is not stored: the step needs only the loss and
+                # the gradients); backward: dL/dc (scatter-add into zeroed arrays)
+                fo = f.data_ptr() if want_f else None
                 if sched:
                     Lb.lsp_eval_mse_scheduled(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, ws.data_ptr(),
-                                              ws_bytes, f.data_ptr(), dldf.data_ptr(), gx.data_ptr(),
-                                              loss.data_ptr(), strm)
+                                              ws_bytes, fo, dldf.data_ptr(), gx.data_ptr(), loss.data_ptr(), strm)
                 else:
-                    Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(),
-                                    dldf.data_ptr(), gx.data_ptr(), loss.data_ptr(), strm)
+                    Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, fo, dldf.data_ptr(),
+                                    gx.data_ptr(), loss.data_ptr(), strm)
                 mark(marks, 1)
                 for g in gradc:
                     g.zero_()
@@ -268,8 +269,8 @@ def main():
                 else:
                     Lb.lsp_eval_adjoint(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
                                         [g.data_ptr() for g in gradc], None, strm)
-            # fwd: x + y + coefficients + f + dL/df + dL/dx; bwd: x + dL/df + scatter (4 B per site)
-            bytes_fwd = 4 * s + 4 + Lq * bytes_c + 8 + 4 * s
+            # fwd: x + y + coefficients + dL/df + dL/dx; bwd: x + dL/df + scatter (4 B per site)
+            bytes_fwd = 4 * s + 4 + Lq * bytes_c + 4 + 4 * s
             bytes_bwd = 4 * s + 4 + Lq * 4
             bytes_per = bytes_fwd + bytes_bwd
             kernels = "forward + backward kernels (MSE forward with dL/dx, adjoint scatter)"
@@ -349,6 +350,9 @@ def main():
         del junk
         rec["roofline"]["copy_gbs"] = round(copy_bandwidth(torch), 1)
     if not args.no_cpu and X is not None:
+        if cfg.passes == "mse":
+            step(None, want_f=True)        # untimed: store f for the accuracy check
+            torch.cuda.synchronize()
         log("[bench] CPU oracle leg")
         cb, idx, want = cpu_baseline(args.config, coeffs if tdt != torch.float32 else
                                      [c.astype(np.float32) for c in coeffs], X)

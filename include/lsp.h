@@ -107,7 +107,8 @@ lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void*
                     void* stream);
 
 /* Forward with a mean-squared-error head against targets y (N float32):
- * writes f, dL/df = 2 (f - y) / N, and adds L = sum (f - y)^2 / N to *loss
+ * writes f (unless f is NULL: a training step needs only the loss and the
+ * gradients), dL/df = 2 (f - y) / N, and adds L = sum (f - y)^2 / N to *loss
  * (float64; the caller zeroes it).  If dloss_dx is not NULL it also receives
  * dL/dx = dL/df * grad f (N x s) -- the loss gradient for the queries, known
  * already in the forward pass.  Float32/bf16/f16 volumes. */

@@ -118,21 +118,22 @@ class LatticeSpline:
         if schedule.n != x.shape[0] or schedule.x.data_ptr() != x.data_ptr():
             raise ValueError("the schedule was built for other queries")
 
-    def eval_mse(self, vol, x, y, schedule=None, grad_x=False):
-        """f, dL/df, L (and dL/dx if grad_x) for L = mean (f - y)^2."""
+    def eval_mse(self, vol, x, y, schedule=None, grad_x=False, want_f=True):
+        """f, dL/df, L (and dL/dx if grad_x) for L = mean (f - y)^2; f is None
+        when want_f is False (the step then stores only the loss and gradients)."""
         _require_device(x, y)
         n = x.shape[0]
-        f = torch.empty(n, device=x.device, dtype=torch.float32)
+        f = torch.empty(n, device=x.device, dtype=torch.float32) if want_f else None
         dldf = torch.empty(n, device=x.device, dtype=torch.float32)
         dldx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
         loss = torch.zeros(1, device=x.device, dtype=torch.float64)
         if schedule is None:
-            L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, f.data_ptr(), dldf.data_ptr(),
+            L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, _ptr(f), dldf.data_ptr(),
                            _ptr(dldx), loss.data_ptr(), _stream())
         else:
             self._check_sched(schedule, x)
             L.lsp_eval_mse_scheduled(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, schedule.ws.data_ptr(),
-                                     schedule.bytes, f.data_ptr(), dldf.data_ptr(), _ptr(dldx), loss.data_ptr(),
+                                     schedule.bytes, _ptr(f), dldf.data_ptr(), _ptr(dldx), loss.data_ptr(),
                                      _stream())
         return (f, dldf, loss, dldx) if grad_x else (f, dldf, loss)
 

@@ -312,7 +312,7 @@ lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float*
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
   if (n == 0) return LSP_OK;
-  if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
+  if (!x || !y || !dloss_df || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, nullptr, f, dloss_df, dloss_dx, loss, s)
@@ -427,7 +427,7 @@ lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, co
   if (n < 0) return LSP_ERR_INVALID;
   if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
   if (n == 0) return LSP_OK;
-  if (!x || !y || !f || !dloss_df || !loss) return LSP_ERR_NULL;
+  if (!x || !y || !dloss_df || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, workspace, f, dloss_df, dloss_dx, loss, s)

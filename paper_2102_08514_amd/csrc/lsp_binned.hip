@@ -587,7 +587,7 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
 #pragma unroll
       for (int kk = 0; kk < SP::M; ++kk)
         coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds + kk * si.vol, kk, xq, acc, gx);
-      f[q] = acc;
+      if (f) f[q] = acc;    // optional for the MSE head
       AT scale = AT(1);
       if constexpr (MSE) {
         const float r = static_cast<float>(acc) - yq;
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, c
     AT acc = AT(0);
 #pragma unroll
     for (int k = 0; k < SP::M; ++k) acc += fpart[k * n + q];
-    f[q] = acc;
+    if (f) f[q] = acc;      // optional for the MSE head
     AT scale = AT(1);
     if constexpr (MSE) {
       const float r = static_cast<float>(acc) - y[q];

@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restri
     for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, float, GRAD>(vol, kk, xq, acc, gx);
     const float r = acc - y[q];
     const float dl = 2.f * r * inv_n;
-    f[q] = acc;
+    if (f) f[q] = acc;      // optional
     dldf[q] = dl;
     if constexpr (GRAD) {
 #pragma unroll

@@ -161,6 +161,11 @@ def test_mse_head(lsp, name):
         assert abs(float(loss.item()) - float(np.mean(r * r))) <= 1e-5 * max(1.0, float(np.mean(r * r)))
         # dL/dx = dL/df * grad f
         np.testing.assert_allclose(dldx.cpu().numpy(), (2 * r / n)[:, None] * gw, atol=1e-4 * 2 / n * 4)
+        # without storing f: the same loss and gradients
+        f2, dldf2, loss2, dldx2 = sp.eval_mse(vol, xd, yd, schedule=sch, grad_x=True, want_f=False)
+        assert f2 is None
+        assert torch.equal(dldf2, dldf) and torch.equal(dldx2, dldx)
+        assert abs(float(loss2.item()) - float(loss.item())) <= 1e-12 * max(1.0, abs(float(loss.item())))
 
 
 def test_autograd_backward_matches_adjoint(lsp):
