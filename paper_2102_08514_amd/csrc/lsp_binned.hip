@@ -786,69 +786,77 @@ __global__ void __launch_bounds__(1024) k_absmax_final(const unsigned* __restric
 }
 
 // 5b. grad_c[k][site] += sum of the private regions of the units covering the
-// site (per axis at most two bricks, since the region width is at most 2B)
+// site.  blockIdx.y is the coset; a block covers a run of 256 sites along
+// axis 0 of one row of the other axes, or, for short rows (n_0 < 256), rpb
+// whole rows.  Every index is 32-bit.
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
 template <class SP, bool SPLIT>
 __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, BinGeom g,
                                                         const unsigned* __restrict__ start,
-                                                        const float* __restrict__ priv, long long sites) {
-  const long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= sites * SP::M) return;
-  const int k = static_cast<int>(e / sites);
-  const long long idx = e - static_cast<long long>(k) * sites;
+                                                        const float* __restrict__ priv, unsigned segs,
+                                                        unsigned rpb, unsigned rows) {
+  constexpr int S = SP::S;
+  constexpr int NC = SPLIT ? 1 : SP::M;
+  constexpr int MG = Staged<SP>::MARGIN;
+  const int k = static_cast<int>(blockIdx.y);
+  const unsigned d0 = static_cast<unsigned>(vol.dims[0]);
+  const unsigned blk = blockIdx.x / segs;
+  const unsigned seg = blockIdx.x - blk * segs;
+  const unsigned roff = rpb == 1 ? 0u : threadIdx.x / d0;
+  int c[S];
+  c[0] = static_cast<int>(rpb == 1 ? seg * 256u + threadIdx.x : threadIdx.x - roff * d0);
+  const unsigned row = blk * rpb + roff;
+  if (roff >= rpb || c[0] >= static_cast<int>(d0) || row >= rows) return;
+  {
+    unsigned r = row;
+#pragma unroll
+    for (int d = 1; d < S; ++d) {
+      c[d] = static_cast<int>(r % static_cast<unsigned>(vol.dims[d]));
+      r /= static_cast<unsigned>(vol.dims[d]);
+    }
+  }
   const int B = 1 << g.bshift;
   const int W = Staged<SP>::width(B);
-  int c[SP::S], blo[SP::S], bhi[SP::S];
-  long long rem = idx;
+  const int vol_r = Staged<SP>::volume(B);
+  // bricks b whose region [b B - MARGIN + OMIN, b B + B - 1 + OMAX] holds c
+  int blo[S], bcnt[S];
 #pragma unroll
-  for (int d = 0; d < SP::S; ++d) {
-    c[d] = static_cast<int>(rem % vol.dims[d]);
-    rem /= vol.dims[d];
-    // bricks b whose region [b B - MARGIN + OMIN, b B + B - 1 + OMAX] holds c
-    int lo = c[d] - (B - 1 + SP::OMAX);
-    lo = lo <= 0 ? 0 : (lo + B - 1) / B;
-    int hi = (c[d] + Staged<SP>::MARGIN - SP::OMIN) / B;
+  for (int d = 0; d < S; ++d) {
+    int lo = floor_div(c[d] - (B - 1 + SP::OMAX) + B - 1, B);
+    int hi = floor_div(c[d] + MG - SP::OMIN, B);
+    lo = lo < 0 ? 0 : lo;
     hi = hi >= g.nb[d] ? g.nb[d] - 1 : hi;
     blo[d] = lo;
-    bhi[d] = hi;
+    bcnt[d] = hi - lo + 1;
   }
-  constexpr int NC = SPLIT ? 1 : SP::M;
-  const int vol_r = Staged<SP>::volume(B);
   float sum = 0.f;
-  int b[SP::S];
+  const int n3 = S == 4 ? bcnt[S - 1] : 1;
+  for (int i3 = 0; i3 < n3; ++i3)
+    for (int i2 = 0; i2 < bcnt[2]; ++i2)
+      for (int i1 = 0; i1 < bcnt[1]; ++i1)
+        for (int i0 = 0; i0 < bcnt[0]; ++i0) {
+          const int idx[4] = {i0, i1, i2, i3};
+          unsigned brick = 0, mul = 1;
+          int local = 0, ls = 1;
 #pragma unroll
-  for (int d = 0; d < SP::S; ++d) b[d] = blo[d];
-  for (;;) {
-    bool ok = true;
+          for (int d = 0; d < S; ++d) {
+            const int b = blo[d] + idx[d];
+            brick += static_cast<unsigned>(b) * mul;
+            mul *= static_cast<unsigned>(g.nb[d]);
+            local += (c[d] - (b * B - MG + SP::OMIN)) * ls;
+            ls *= W;
+          }
+          const unsigned unit = brick * g.upb + (SPLIT ? static_cast<unsigned>(k) : 0u);
+          const unsigned k0 = unit * g.kpb;
+          if (start[k0] != start[k0 + g.kpb])
+            sum += priv[(static_cast<size_t>(unit) * NC + (SPLIT ? 0 : k)) * vol_r + local];
+        }
+  long long off = 0;
 #pragma unroll
-    for (int d = 0; d < SP::S; ++d) ok = ok && (b[d] <= bhi[d]);
-    if (ok) {
-      long long brick = 0, mul = 1;
-      int local = 0, ls = 1;
-#pragma unroll
-      for (int d = 0; d < SP::S; ++d) {
-        brick += static_cast<long long>(b[d]) * mul;
-        mul *= g.nb[d];
-        local += (c[d] - (b[d] * B - Staged<SP>::MARGIN + SP::OMIN)) * ls;
-        ls *= W;
-      }
-      const long long unit = brick * g.upb + (SPLIT ? k : 0);
-      const unsigned k0 = static_cast<unsigned>(unit) * g.kpb;
-      if (start[k0] != start[k0 + g.kpb])
-        sum += priv[(static_cast<size_t>(unit) * NC + (SPLIT ? 0 : k)) * vol_r + local];
-    }
-    // next combination (odometer over the brick ranges)
-    int d = 0;
-    for (; d < SP::S; ++d) {
-      if (b[d] < bhi[d]) {
-        ++b[d];
-        break;
-      }
-      b[d] = blo[d];
-    }
-    if (d == SP::S) break;
-  }
+  for (int d = 0; d < S; ++d) off += static_cast<long long>(c[d]) * vol.stride[d];
   float* gc = pick<SP::M>(gvol.base, k);
-  gc[idx] += sum;
+  gc[off] += sum;
 }
 
 // sum the per-coset grad_x partials of a split adjoint

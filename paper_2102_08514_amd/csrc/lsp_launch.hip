@@ -233,7 +233,12 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   }
   const Bin bn = make_bin<SP>(v, n);
   const BinGeom& gm = bn.g;
-  if (bn.lds_adj_g > kLdsMax) {
+  // the gather pass: one block per 256-site run along axis 0 of each row of
+  // the other axes, per coset
+  const unsigned segs = grid_of(v->vol.dims[0]);
+  unsigned long long rows = 1;
+  for (int d = 1; d < SP::S; ++d) rows *= static_cast<unsigned long long>(v->vol.dims[d]);
+  if (bn.lds_adj_g > kLdsMax || rows * segs > 0x7fffffffull) {
     // a unit's region does not fit in LDS (large 4-D bricks): scatter-add
     // with global atomics in the given order
     if (grad_x)
@@ -270,10 +275,10 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
     hipLaunchKernelGGL((k_adjoint_binned<SP, CT, false, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
                        recs, start, g, gx_out, priv, gmax);
   }
-  long long sites = 1;
-  for (int d = 0; d < SP::S; ++d) sites *= v->vol.dims[d];
-  hipLaunchKernelGGL((k_adjoint_gather<SP, SPLIT>), dim3(grid_of(sites * SP::M)), dim3(256), 0, st, v->vol, gv, gm,
-                     start, priv, sites);
+  const unsigned rpb = v->vol.dims[0] >= 256 ? 1u : 256u / static_cast<unsigned>(v->vol.dims[0]);
+  const unsigned blocks = static_cast<unsigned>((rows + rpb - 1) / rpb) * segs;
+  hipLaunchKernelGGL((k_adjoint_gather<SP, SPLIT>), dim3(blocks, SP::M), dim3(256), 0, st, v->vol, gv, gm, start, priv,
+                     segs, rpb, static_cast<unsigned>(rows));
   if (SPLIT && grad_x)
     hipLaunchKernelGGL((k_combine_gx<SP>), dim3(grid_of(n * SP::S)), dim3(256), 0, st, gx_out,
                        static_cast<long long>(n), grad_x);
