@@ -146,7 +146,7 @@ def _mesh_breakpoints(Xi_sub, x, xi):
     return sorted(ts)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5", "d4", "cc_linear_rd", "bcc_quintic_rd"])
 def test_convolution_definition(name):
     """M_Xi(x) = int_0^1 M_{Xi\\xi}(x - t xi) dt (Sec. 3, sign corrected),
     integrated exactly: the integrand is a polynomial of degree n-1-s between
@@ -204,7 +204,7 @@ def _order(Xi):
     return n
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4", "cc_linear_rd", "bcc_quintic_rd"])
 def test_moment_identities(name):
     """For |alpha| < m (Strang--Fix), sum_{n in L} (x-n)^alpha phi(x-n) equals
     int y^alpha phi(y) dy / ... = E[(Xi v)^alpha], v ~ U[-1/2,1/2]^n, at every x."""
@@ -212,7 +212,8 @@ def test_moment_identities(name):
     o = ConvolutionSumOracle(cfg.L, cfg.Xi)
     s = cfg.s
     m = _order(cfg.Xi)
-    assert m == {"c1": 2, "c2": 4, "c3": 4, "c4": 3, "c5": 4}[name]
+    # orders printed in Table 1; the D4 spline is fourth order (Sec. 5.2)
+    assert m == {"c1": 2, "c2": 4, "c3": 4, "c4": 3, "c5": 4, "d4": 4, "cc_linear_rd": 2, "bcc_quintic_rd": 4}[name]
     dims = (12,) * s
     X = f32(RNG.uniform(4.5, 2 * 12 - 6.5 if cfg.D == 2 else 12 - 4.5, (8 if s == 4 else 30, s)))
     qi, ki, flat, Wd = o._candidates(X, dims)
