@@ -177,8 +177,8 @@ def main():
                     help="evaluate in the library's scheduled order (timed) or in the given order")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the method has no cross-GPU step in this build "
-              "(queries shard trivially; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the evaluation shards over queries with no exchange in the forward "
+              "pass, and only the single-GPU kernel is timed. Run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
