@@ -304,6 +304,14 @@ def main():
     ev_med = float(pmed[1:].sum()) if nm else float(pmed[0])
     achieved = bytes_per * n / ev_mean / 1e9
     traffic = measured_traffic(args.config, dname)
+    # compulsory floor: the coefficient volume once, the queries once, the outputs once
+    vol_bytes = sum(int(np.prod(c.shape)) for c in dev) * bytes_c
+    if X is None:
+        compulsory = vol_bytes + (W_ * H_) * 16
+    elif cfg.passes == "mse":
+        compulsory = vol_bytes + n * (4 * s + 4 + 4 + 4 * s) + sum(int(np.prod(c.shape)) for c in dev) * 4
+    else:
+        compulsory = vol_bytes + n * (4 * s + out_b)
     rec = {
         "metric": "Gsamples/s fwd and fwd+bwd at stated max err vs FP64 oracle; % HBM roofline",
         "value": round(value, 4),
@@ -326,7 +334,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else traffic["bytes_per_launch"],
                      "kernel": kernels, "algorithmic_bytes_per_sample": round(bytes_per, 3),
-                     "samples_per_launch": n,
+                     "samples_per_launch": n, "compulsory_bytes": int(compulsory),
+                     "compulsory_floor_ms": round(compulsory / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
                      "eval_ms_mean": round(ev_mean * 1e3, 4), "eval_ms_median": round(ev_med * 1e3, 4)},
         "phases_ms_mean": {p: round(float(v) * 1e3, 4) for p, v in zip(phases, pmean)},
         "kernel_source_digest": kernel_source_digest(),
