@@ -11,8 +11,10 @@
  * directions) and scaled to a partition of unity on the lattice (the
  * requirement on phi stated in Sec. 4.1), at many query points, with the
  * paper's fast scheme (Sec. 4, Algorithm 1).  It also gives the spatial
- * gradient, the adjoint (transpose) of c -> f, a mean-squared-error head and
- * a ray-marching sample generator.
+ * gradient, the adjoint (transpose) of c -> f, a mean-squared-error head, a
+ * ray-marching sample generator and a volume renderer (Sec. 5.1), and a
+ * cache-friendly evaluation order for large random query batches
+ * (lsp_schedule and the *_scheduled entry points).
  *
  * Conventions
  *  - Status: every function returns lsp_status (0 = LSP_OK, < 0 error); no
