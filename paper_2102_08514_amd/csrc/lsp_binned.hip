@@ -70,8 +70,9 @@ template <class SP> struct Staged {
   // Per coset the staged cells are [b B - MARGIN + OMIN, b B + B - 1 + OMAX]
   // per axis.  A whole-query item is binned by its coset-0 cell, and another
   // coset's cell index can be one less (MARGIN = 1); a (query, coset) item is
-  // binned by its own coset's cell (MARGIN = 0).
-  static constexpr int MARGIN = SplitPolicy<SP>::value ? 0 : 1;
+  // binned by its own coset's cell, and a one-coset lattice has no other
+  // coset (MARGIN = 0).
+  static constexpr int MARGIN = (SplitPolicy<SP>::value || SP::M == 1) ? 0 : 1;
   __host__ __device__ static constexpr int width(int B) { return B + MARGIN + SP::OMAX - SP::OMIN; }
   __host__ __device__ static constexpr int volume(int B) {
     int v = 1;
