@@ -47,6 +47,7 @@ struct BinGeom {
   long long tile_items;
   long long n;          // queries
   long long items;      // work items (n, or n * M when split)
+  unsigned wpu;         // evaluation workgroups per unit (several when units are few)
 };
 
 // Work items are (query, coset) pairs, grouped by sub-region, when the spline
@@ -522,9 +523,14 @@ struct UnitRange {
 };
 
 template <bool SPLIT>
-__device__ __forceinline__ bool unit_range(const BinGeom& g, const unsigned* start, UnitRange& u) {
-  u.unit = unit_of_block(g.nunits);
-  if (u.unit < 0) return false;
+__device__ __forceinline__ bool unit_range(const BinGeom& g, const unsigned* start, UnitRange& u,
+                                           unsigned wpu = 1, unsigned* part = nullptr) {
+  // with wpu > 1 consecutive virtual blocks share a unit, each taking every
+  // wpu-th run of blockDim.x items
+  const long long vb = unit_of_block(g.nunits * wpu);
+  if (vb < 0) return false;
+  u.unit = vb / wpu;
+  if (part) *part = static_cast<unsigned>(vb - u.unit * wpu);
   u.brick = u.unit / g.upb;
   u.kunit = SPLIT ? static_cast<int>(u.unit - u.brick * g.upb) : 0;
   const unsigned k0 = static_cast<unsigned>(u.unit) * g.kpb;
@@ -545,7 +551,8 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
   extern __shared__ unsigned char smem[];
   AT* lds = reinterpret_cast<AT*>(smem);
   UnitRange u;
-  if (!unit_range<SPLIT>(g, start, u)) return;
+  unsigned part = 0;
+  if (!unit_range<SPLIT>(g, start, u, g.wpu, &part)) return;
   StageInfo<SP, AT> si;
   stage_info<SP, AT>(g, u.brick, si);
   if constexpr (STAGE) {
@@ -553,12 +560,14 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
     __syncthreads();
   }
   float r2 = 0.f;
+  const unsigned step = g.wpu * blockDim.x;
+  const unsigned first = u.lo + part * blockDim.x + threadIdx.x;
   // the next record is loaded while this one is evaluated
-  Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, u.hi - 1)];
+  Rec<SP::S> cur = recs[min(first, u.hi - 1)];
   float ycur = 0.f;
   if constexpr (MSE && !SPLIT) ycur = y[rec_query<SP, SPLIT>(cur)];
-  for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
-    const Rec<SP::S> nxt = recs[min(t + blockDim.x, u.hi - 1)];
+  for (unsigned t = first; t < u.hi; t += step) {
+    const Rec<SP::S> nxt = recs[min(t + step, u.hi - 1)];
     float ynxt = 0.f;
     if constexpr (MSE && !SPLIT) ynxt = y[rec_query<SP, SPLIT>(nxt)];
     float xf[SP::S];

@@ -22,6 +22,8 @@ using namespace lsp;
 constexpr size_t kLdsMax = 160 * 1024;    // LDS of one gfx950 workgroup
 constexpr size_t kLdsEval = 64 * 1024;    // keep several evaluation workgroups per CU
 constexpr int kAbsMaxParts = 1024;         // blocks of the max |g| reduction
+constexpr unsigned long long kMinUnits = 1024;        // fewer units than this: smaller bricks
+constexpr unsigned long long kMinEvalGroups = 2048;   // fewer units than this: several workgroups per unit
 // key histogram budget: 3-D bricks stay at 16^3 cells for the big volumes
 // (fewer, fuller bricks amortise the staged halo); 4-D needs the full LDS to
 // keep 8^4 bricks with sub-region keys
@@ -55,7 +57,17 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   g.items = bn.split ? n * SP::M : n;
   g.upb = bn.split ? SP::M : 1;
   g.kpb = bn.split ? SP::K : 1;
-  for (g.bshift = 3;; ++g.bshift) {
+  // the smallest brick (from 8 cells a side) whose key histogram fits the
+  // LDS budget; 4-cell bricks when 8-cell ones would leave fewer than
+  // kMinUnits units, too few workgroups to balance 256 CUs
+  auto units_at = [&](int bshift) {
+    unsigned long long nbr = 1;
+    for (int d = 0; d < SP::S; ++d)
+      nbr *= static_cast<unsigned long long>((v->vol.dims[d] + (1 << bshift) - 1) >> bshift);
+    return nbr;
+  };
+  g.bshift = units_at(3) * g.upb < kMinUnits && units_at(2) * g.upb * g.kpb * 4 <= hist_budget<SP>() ? 2 : 3;
+  for (;; ++g.bshift) {
     unsigned long long nbr = 1;
     for (int d = 0; d < SP::S; ++d) {
       g.nb[d] = (v->vol.dims[d] + (1 << g.bshift) - 1) >> g.bshift;
@@ -67,6 +79,13 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
       g.nkeys = static_cast<unsigned>(nbr * g.upb * g.kpb);
       break;
     }
+  }
+  // evaluation workgroups per unit: enough for kMinEvalGroups workgroups in
+  // all, as long as each still gets 2048 items or more on average
+  {
+    const unsigned long long want = (kMinEvalGroups + g.nunits - 1) / g.nunits;
+    const unsigned long long fill = static_cast<unsigned long long>(g.items) / (2048ull * g.nunits);
+    g.wpu = static_cast<unsigned>(std::max<unsigned long long>(1, std::min<unsigned long long>({8, want, fill})));
   }
   g.tiles = static_cast<int>(std::max<long long>(1, std::min<long long>(256, (g.items + 4095) / 4096)));
   g.tile_items = (g.items + g.tiles - 1) / g.tiles;
@@ -131,7 +150,7 @@ lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT*
   const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
   constexpr bool SPLIT = SplitPolicy<SP>::value;
   const float inv_n = 1.0f / static_cast<float>(n);
-  const dim3 grid(unit_grid(g.nunits));
+  const dim3 grid(unit_grid(g.nunits * g.wpu));
   // the unit's coefficients are staged in LDS when the region fits
   constexpr int NT = SP::S == 3 ? 256 : 512;
 #define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                                 \

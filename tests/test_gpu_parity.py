@@ -376,3 +376,30 @@ def test_scheduled_adjoint_fixed_point_scaling(lsp, name):
 
 def cfg_s(name):
     return W.get(name).s
+
+
+@pytest.mark.parametrize("name,n", [("c4", 200000), ("d4", 70000)])
+def test_scheduled_several_groups_per_unit(lsp, name, n):
+    """Few units with many items each: the evaluation splits every unit over
+    several workgroups; results match the given-order path (and the MSE head
+    its loss)."""
+    torch = _torch()
+    cfg = W.get(name)
+    dims = SMALL[name]
+    rng = np.random.default_rng(40)
+    coeffs = [rng.uniform(-1, 1, tuple(reversed(dims))) for _ in range(cfg.M)]
+    ext = cfg.D * (dims[0] - 1) + 1
+    X = rng.uniform(2.0, ext - 3.0, (n, cfg.s)).astype(np.float32)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    x = torch.from_numpy(X).cuda()
+    f0, g0 = sp.eval(vol, x, grad=True)
+    sch = sp.schedule(vol, x)
+    f1, g1 = sp.eval(vol, x, grad=True, schedule=sch)
+    assert normwise(f1.cpu().numpy(), f0.cpu().numpy(), coeffs) <= 1e-6
+    assert normwise(g1.cpu().numpy(), g0.cpu().numpy(), coeffs) <= 1e-5
+    y = torch.from_numpy(I.targets(cfg, X)).cuda()
+    _, da, la = sp.eval_mse(vol, x, y)
+    _, db, lb = sp.eval_mse(vol, x, y, schedule=sch)
+    assert float((da - db).abs().max()) <= 1e-9
+    assert abs(float(la) - float(lb)) <= 1e-6 * max(1.0, abs(float(la)))
