@@ -192,7 +192,10 @@ lsp_status lsp_render(lsp_plan plan, lsp_vol vol, const float* c, const float* A
  * 64-bit fixed point (scale: a power of two from max |g|, terms resolved to
  * 2^-49 max|g| or finer for units of fewer than 2048 items), so its result does
  * not depend on the order of the additions; a non-finite g makes the
- * affected grad_c entries NaN.  Items whose stencil leaves their unit's
+ * affected grad_c entries NaN, while a query that is not finite adds nothing
+ * to grad_c and gets a NaN grad_x (the given-order adjoint turns that
+ * query's sites NaN).
+ * Items whose stencil leaves their unit's
  * region (queries outside the stored volume), and volumes whose units do
  * not fit in LDS, fall back to float atomics. */
 lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes);

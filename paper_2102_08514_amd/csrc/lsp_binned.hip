@@ -694,6 +694,19 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
     cur = nxt;
     nxt = nn;
     gcur = gnxt;
+    // a query that is not finite adds nothing (fixed point cannot carry NaN);
+    // its grad_x is NaN
+    bool finite = true;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) finite = finite && isfinite(xq[d]);
+    if (!finite) {
+      if constexpr (GRADX) {
+        const long long slot = SPLIT ? static_cast<long long>(k) * g.n + q : q;
+#pragma unroll
+        for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = __int_as_float(0x7fc00000);
+      }
+      continue;
+    }
     float gx[SP::S];
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;

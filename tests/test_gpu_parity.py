@@ -403,3 +403,41 @@ def test_scheduled_several_groups_per_unit(lsp, name, n):
     _, db, lb = sp.eval_mse(vol, x, y, schedule=sch)
     assert float((da - db).abs().max()) <= 1e-9
     assert abs(float(la) - float(lb)) <= 1e-6 * max(1.0, abs(float(la)))
+
+
+@pytest.mark.parametrize("name", ["c4", "c5"])
+def test_scheduled_edge_cases(lsp, name):
+    """Empty batches through every scheduled entry point; queries far outside
+    the volume or not finite through the schedule give what the given-order
+    path gives (zero outside, NaN for NaN, no fault)."""
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, n=301, seed=30)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    s = cfg.s
+    # empty batch
+    e = torch.empty(0, s, device="cuda")
+    sch0 = sp.schedule(vol, e)
+    assert sp.eval(vol, e, schedule=sch0).numel() == 0
+    gc, _ = sp.adjoint(vol, e, torch.empty(0, device="cuda"), schedule=sch0)
+    assert all(float(a.abs().max()) == 0.0 for a in gc)
+    # far outside, non-finite and ordinary queries mixed
+    odd = np.array([[-500.0] * s, [1e7] * s, [np.nan] + [5.0] * (s - 1), [np.inf] + [5.0] * (s - 1)],
+                   dtype=np.float32)
+    Xm = np.concatenate([X, odd]).astype(np.float32)
+    x = torch.from_numpy(Xm).cuda()
+    f0 = sp.eval(vol, x).cpu().numpy()
+    f1 = sp.eval(vol, x, schedule=sp.schedule(vol, x)).cpu().numpy()
+    assert np.array_equal(np.isnan(f0), np.isnan(f1))
+    ok = ~np.isnan(f0)
+    assert np.max(np.abs(f0[ok] - f1[ok])) <= 1e-6
+    assert f1[len(X)] == 0.0 and f1[len(X) + 1] == 0.0 and np.isnan(f1[len(X) + 2])
+    # the scheduled adjoint ignores the non-finite queries (their grad_x is NaN)
+    g = torch.from_numpy(np.random.default_rng(31).normal(size=len(Xm)).astype(np.float32)).cuda()
+    gm, gxm = sp.adjoint(vol, x, g, grad_x=True, schedule=sp.schedule(vol, x))
+    xf = torch.from_numpy(np.ascontiguousarray(Xm[: len(X) + 2])).cuda()
+    gf, gxf = sp.adjoint(vol, xf, g[: len(X) + 2].contiguous(), grad_x=True, schedule=sp.schedule(vol, xf))
+    for a, b in zip(gm, gf):
+        assert float((a - b).abs().max()) <= 1e-6 * max(1.0, float(b.abs().max()))
+    assert bool(torch.isnan(gxm[len(X) + 2:]).all())
+    assert float((gxm[: len(X) + 2] - gxf).abs().max()) <= 1e-6 * max(1.0, float(gxf.abs().max()))
