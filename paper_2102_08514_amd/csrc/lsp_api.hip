@@ -279,6 +279,8 @@ lsp_status lsp_vol_bind(lsp_plan plan, int32_t dtype, const void* const* coset_p
   v->spec = plan->spec;
   v->dtype = dtype;
   v->total = total;
+  const int64_t esize = dtype == LSP_F64 ? 8 : (dtype == LSP_F32 ? 4 : 2);
+  v->vol.bytes32 = total * esize < (int64_t(1) << 32) ? 1 : 0;
   *out = v;
   return LSP_OK;
 }

@@ -47,6 +47,7 @@ struct Vol {
   const void* base[kMaxCosets];
   int dims[kMaxDim];
   int stride[kMaxDim];  // elements
+  int bytes32;          // every coset array spans fewer than 2^32 bytes
 };
 
 struct GradVol {
@@ -232,6 +233,49 @@ struct Gather {
   }
 };
 
+// Interior gather with 32-bit byte offsets from the coset's base: per folded
+// axis the multiples J st_r (bytes) are tabulated once per query, so a site's
+// address is one three-input add, taken by the load as a 32-bit offset to a
+// base that is uniform over the wave.  Needs every coset array below 4 GiB
+// and the whole stencil inside the array (interior queries).
+template <class SP, class CT, class AT>
+struct GatherInterior {
+  static constexpr int JLO = SP::OMIN < 1 - SP::OMAX ? SP::OMIN : 1 - SP::OMAX;
+  static constexpr int JHI = SP::OMAX > 1 - SP::OMIN ? SP::OMAX : 1 - SP::OMIN;
+  static constexpr int NJ = JHI - JLO + 1;
+  const char* base;
+  unsigned p[SP::S][NJ];   // p[r][J - JLO] = J st_r bytes; axis 0 also carries the origin
+
+  __device__ __forceinline__ void init(const Vol& vol, int k, const Folded<SP, AT>& F) {
+    base = static_cast<const char*>(pick<SP::M>(vol.base, k));
+    int off = 0;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) off += F.i[d] * vol.stride[d];
+    int st[SP::S];
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const int sa = axis_stride<SP::S>(vol.dims, F.ax[r]);
+      st[r] = F.sg[r] > 0 ? sa : -sa;
+      if (F.sg[r] < 0) off += sa;
+    }
+#pragma unroll
+    for (int r = 0; r < SP::S; ++r) {
+      const unsigned step = static_cast<unsigned>(st[r]) * static_cast<unsigned>(sizeof(CT));
+      p[r][-JLO] = r == 0 ? static_cast<unsigned>(off) * static_cast<unsigned>(sizeof(CT)) : 0u;
+#pragma unroll
+      for (int j = -JLO + 1; j < NJ; ++j) p[r][j] = p[r][j - 1] + step;
+#pragma unroll
+      for (int j = -JLO - 1; j >= 0; --j) p[r][j] = p[r][j + 1] - step;
+    }
+  }
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ AT c() const {
+    unsigned a = p[0][J0 - JLO] + p[1][J1 - JLO] + p[2][J2 - JLO];
+    if constexpr (SP::S == 4) a += p[3][J3 - JLO];
+    return load_coef<CT, AT>(reinterpret_cast<const CT*>(base + a));
+  }
+};
+
 // Scatter-add of g * w_j into the gradient volume (adjoint, FP32 atomics).
 template <class SP, bool CHECK>
 struct Scatter {
@@ -316,7 +360,11 @@ __device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* x
   fold_query<SP, AT>(xq, k, vol, F);
   const int ob = SP::template orbit<AT>(F.up);
   AT b[SP::NMON];
-  if (F.interior) {
+  if (F.interior && vol.bytes32) {
+    GatherInterior<SP, CT, AT> g;
+    g.init(vol, k, F);
+    SP::template b_any<AT>(ob, g, b);
+  } else if (F.interior) {
     Gather<SP, CT, AT, false> g;
     g.init(vol, k, F);
     SP::template b_any<AT>(ob, g, b);
