@@ -254,8 +254,9 @@ def main():
                 # the gradients); backward: dL/dc (scatter-add into zeroed arrays)
                 fo = f.data_ptr() if want_f else None
                 if sched:
+                    # dL/df stays in the workspace, in schedule order, for the fused backward
                     Lb.lsp_eval_mse_scheduled(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, ws.data_ptr(),
-                                              ws_bytes, fo, dldf.data_ptr(), gx.data_ptr(), loss.data_ptr(), strm)
+                                              ws_bytes, fo, None, gx.data_ptr(), loss.data_ptr(), strm)
                 else:
                     Lb.lsp_eval_mse(sp.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, fo, dldf.data_ptr(),
                                     gx.data_ptr(), loss.data_ptr(), strm)
@@ -263,9 +264,8 @@ def main():
                 for g in gradc:
                     g.zero_()
                 if sched:
-                    Lb.lsp_eval_adjoint_scheduled(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
-                                                  ws.data_ptr(), ws_bytes, [g.data_ptr() for g in gradc], None,
-                                                  strm)
+                    Lb.lsp_mse_backward_scheduled(sp.plan, vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes,
+                                                  [g.data_ptr() for g in gradc], strm)
                 else:
                     Lb.lsp_eval_adjoint(sp.plan, vol.handle, x.data_ptr(), dldf.data_ptr(), n,
                                         [g.data_ptr() for g in gradc], None, strm)

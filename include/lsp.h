@@ -110,7 +110,8 @@ lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void*
 
 /* Forward with a mean-squared-error head against targets y (N float32):
  * writes f (unless f is NULL: a training step needs only the loss and the
- * gradients), dL/df = 2 (f - y) / N, and adds L = sum (f - y)^2 / N to *loss
+ * gradients), dL/df = 2 (f - y) / N (unless dloss_df is NULL), and adds
+ * L = sum (f - y)^2 / N to *loss
  * (float64; the caller zeroes it).  If dloss_dx is not NULL it also receives
  * dL/dx = dL/df * grad f (N x s) -- the loss gradient for the queries, known
  * already in the forward pass.  Float32/bf16/f16 volumes. */
@@ -209,6 +210,16 @@ lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, co
 lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x, const float* g, int64_t n,
                                       const void* workspace, size_t ws_bytes, float* const* grad_c, float* grad_x,
                                       void* stream);
+
+/* The backward of a scheduled MSE step without handing dL/df back and forth:
+ * adds sum_q (dL/df)_q phi(x_q - site) into grad_c (as lsp_eval_adjoint_
+ * scheduled with g = dL/df), reading the dL/df that the preceding
+ * lsp_eval_mse_scheduled call on the same queries and workspace left in the
+ * workspace (in schedule order, so the reads are coalesced).  With this call
+ * that forward may pass dloss_df = NULL.  LSP_ERR_UNSUPPORTED when the
+ * volume's units do not fit in LDS (use lsp_eval_adjoint_scheduled then). */
+lsp_status lsp_mse_backward_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
+                                      size_t ws_bytes, float* const* grad_c, void* stream);
 
 const char* lsp_status_string(lsp_status status);
 

@@ -17,7 +17,7 @@ EXPORTS = (
     "lsp_plan_create", "lsp_plan_info", "lsp_plan_destroy", "lsp_vol_bind", "lsp_vol_release",
     "lsp_eval", "lsp_eval_mse", "lsp_eval_adjoint", "lsp_eval_rays", "lsp_status_string",
     "lsp_schedule_size", "lsp_schedule", "lsp_eval_scheduled", "lsp_eval_mse_scheduled",
-    "lsp_eval_adjoint_scheduled", "lsp_render",
+    "lsp_eval_adjoint_scheduled", "lsp_render", "lsp_mse_backward_scheduled",
 )
 
 
@@ -74,6 +74,7 @@ def lib():
         L.lsp_eval_adjoint_scheduled.argtypes = [vp, vp, vp, vp, i64, vp, sz, P(vp), vp, vp]
         L.lsp_render.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), i32, i32, i32, i64, i64, vp,
                                  P(LspRenderParams), vp, vp]
+        L.lsp_mse_backward_scheduled.argtypes = [vp, vp, vp, i64, vp, sz, P(vp), vp]
         L.lsp_status_string.argtypes = [i32]
         L.lsp_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -194,3 +195,9 @@ def lsp_render(plan, vol, c, A, W, H, steps, ray0, nrays, tf_ptr, params, rgba_p
                                                   "tf_len")})
     check(lib().lsp_render(plan, vol, cc, AA, int(W), int(H), int(steps), int(ray0), int(nrays), tf_ptr,
                            ctypes.byref(p), rgba_ptr, stream), "lsp_render")
+
+
+def lsp_mse_backward_scheduled(plan, vol, x_ptr, n, ws_ptr, ws_bytes, grad_c_ptrs, stream):
+    arr = (ctypes.c_void_p * len(grad_c_ptrs))(*[int(p) for p in grad_c_ptrs])
+    check(lib().lsp_mse_backward_scheduled(plan, vol, x_ptr, int(n), ws_ptr, int(ws_bytes), arr, stream),
+          "lsp_mse_backward_scheduled")

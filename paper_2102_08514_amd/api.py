@@ -118,24 +118,37 @@ class LatticeSpline:
         if schedule.n != x.shape[0] or schedule.x.data_ptr() != x.data_ptr():
             raise ValueError("the schedule was built for other queries")
 
-    def eval_mse(self, vol, x, y, schedule=None, grad_x=False, want_f=True):
-        """f, dL/df, L (and dL/dx if grad_x) for L = mean (f - y)^2; f is None
-        when want_f is False (the step then stores only the loss and gradients)."""
+    def eval_mse(self, vol, x, y, schedule=None, grad_x=False, want_f=True, want_dldf=True):
+        """f, dL/df, L (and dL/dx if grad_x) for L = mean (f - y)^2; f (dL/df)
+        is None when want_f (want_dldf) is False.  With a schedule, dL/df also
+        stays in the schedule's workspace for mse_backward."""
         _require_device(x, y)
         n = x.shape[0]
         f = torch.empty(n, device=x.device, dtype=torch.float32) if want_f else None
-        dldf = torch.empty(n, device=x.device, dtype=torch.float32)
+        dldf = torch.empty(n, device=x.device, dtype=torch.float32) if want_dldf else None
         dldx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
         loss = torch.zeros(1, device=x.device, dtype=torch.float64)
         if schedule is None:
-            L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, _ptr(f), dldf.data_ptr(),
+            L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, _ptr(f), _ptr(dldf),
                            _ptr(dldx), loss.data_ptr(), _stream())
         else:
             self._check_sched(schedule, x)
             L.lsp_eval_mse_scheduled(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, schedule.ws.data_ptr(),
-                                     schedule.bytes, _ptr(f), dldf.data_ptr(), _ptr(dldx), loss.data_ptr(),
+                                     schedule.bytes, _ptr(f), _ptr(dldf), _ptr(dldx), loss.data_ptr(),
                                      _stream())
         return (f, dldf, loss, dldx) if grad_x else (f, dldf, loss)
+
+    def mse_backward(self, vol, x, schedule, grad_c=None):
+        """grad_c (zero-initialised here unless given) += A^T dL/df, with the
+        dL/df that the preceding eval_mse(schedule=schedule) left in the
+        schedule's workspace."""
+        _require_device(x)
+        self._check_sched(schedule, x)
+        if grad_c is None:
+            grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
+        L.lsp_mse_backward_scheduled(self.plan, vol.handle, x.data_ptr(), x.shape[0], schedule.ws.data_ptr(),
+                                     schedule.bytes, [t.data_ptr() for t in grad_c], _stream())
+        return grad_c
 
     def adjoint(self, vol, x, g, grad_x=False, grad_c=None, schedule=None):
         """grad_c (zero-initialised here unless given) += A^T g; grad_x = g * grad f."""

@@ -314,7 +314,7 @@ lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float*
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
   if (n == 0) return LSP_OK;
-  if (!x || !y || !dloss_df || !loss) return LSP_ERR_NULL;
+  if (!x || !y || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, nullptr, f, dloss_df, dloss_dx, loss, s)
@@ -332,7 +332,7 @@ lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const fl
     if (!grad_c[k]) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, nullptr, grad_c, grad_x, s)
+  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, nullptr, grad_c, grad_x, s, false)
 }
 
 lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float* A, int32_t W, int32_t H,
@@ -429,7 +429,7 @@ lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, co
   if (n < 0) return LSP_ERR_INVALID;
   if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
   if (n == 0) return LSP_OK;
-  if (!x || !y || !dloss_df || !loss) return LSP_ERR_NULL;
+  if (!x || !y || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, workspace, f, dloss_df, dloss_dx, loss, s)
@@ -449,7 +449,23 @@ lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x
     if (!grad_c[k]) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, workspace, grad_c, grad_x, s)
+  LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, workspace, grad_c, grad_x, s, false)
+}
+
+lsp_status lsp_mse_backward_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
+                                      size_t ws_bytes, float* const* grad_c, void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if (n == 0) return LSP_OK;
+  if (!x || !grad_c) return LSP_ERR_NULL;
+  const SpecDesc& sd = specs()[plan->spec];
+  for (int k = 0; k < sd.M; ++k)
+    if (!grad_c[k]) return LSP_ERR_NULL;
+  if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LSP_DISPATCH(plan->spec, adj_spec, vol, x, nullptr, n, workspace, grad_c, nullptr, s, true)
 }
 
 }  // extern "C"

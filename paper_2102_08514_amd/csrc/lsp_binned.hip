@@ -547,7 +547,8 @@ template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool 
 __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
                                                      const unsigned* __restrict__ start, AT* __restrict__ f,
                                                      AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
-                                                     float* __restrict__ dldf, double* __restrict__ loss) {
+                                                     float* __restrict__ dldf, double* __restrict__ loss,
+                                                     float* __restrict__ gsave) {
   extern __shared__ unsigned char smem[];
   AT* lds = reinterpret_cast<AT*>(smem);
   UnitRange u;
@@ -602,7 +603,8 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
       if constexpr (MSE) {
         const float r = static_cast<float>(acc) - yq;
         const float dl = 2.f * r * inv_n;
-        dldf[q] = dl;
+        if (dldf) dldf[q] = dl;
+        if (gsave) gsave[t] = dl;   // in schedule order, for the fused backward
         r2 += r * r;
         scale = static_cast<AT>(dl);
       }
@@ -621,7 +623,7 @@ template <class SP, class AT, bool GRAD, bool MSE>
 __global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, const AT* __restrict__ gpart,
                                                  long long n, AT* __restrict__ f, AT* __restrict__ grad,
                                                  const float* __restrict__ y, float inv_n, float* __restrict__ dldf,
-                                                 double* __restrict__ loss) {
+                                                 double* __restrict__ loss, float* __restrict__ gsave) {
   float r2 = 0.f;
   for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < n;
        q += static_cast<long long>(gridDim.x) * blockDim.x) {
@@ -633,7 +635,8 @@ __global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, c
     if constexpr (MSE) {
       const float r = static_cast<float>(acc) - y[q];
       const float dl = 2.f * r * inv_n;
-      dldf[q] = dl;
+      if (dldf) dldf[q] = dl;
+      if (gsave) gsave[q] = dl;     // by query, for the fused backward
       r2 += r * r;
       scale = static_cast<AT>(dl);
     }
@@ -661,7 +664,8 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
                                                         const Rec<SP::S>* __restrict__ recs,
                                                         const unsigned* __restrict__ start,
                                                         const float* __restrict__ gout, float* __restrict__ grad_x,
-                                                        float* __restrict__ priv, const unsigned* __restrict__ gmax_bits) {
+                                                        float* __restrict__ priv, const unsigned* __restrict__ gmax_bits,
+                                                        int g_sorted) {
   extern __shared__ unsigned char smem[];
   UnitRange u;
   if (!unit_range<SPLIT>(g, start, u)) return;
@@ -678,13 +682,14 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
   // software pipeline: records are loaded two queries ahead, the (randomly
   // placed) upstream gradient one query ahead, so a whole query's work hides
   // each load
+  // g_sorted: gout holds g in schedule order (item t), else by query
   const unsigned last = u.hi - 1;
   Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, last)];
   Rec<SP::S> nxt = recs[min(u.lo + threadIdx.x + blockDim.x, last)];
-  float gcur = gout[rec_query<SP, SPLIT>(cur)];
+  float gcur = g_sorted ? gout[min(u.lo + threadIdx.x, last)] : gout[rec_query<SP, SPLIT>(cur)];
   for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
     const Rec<SP::S> nn = recs[min(t + 2 * blockDim.x, last)];
-    const float gnxt = gout[rec_query<SP, SPLIT>(nxt)];
+    const float gnxt = g_sorted ? gout[min(t + blockDim.x, last)] : gout[rec_query<SP, SPLIT>(nxt)];
     float xq[SP::S];
     const unsigned item = rec_item<SP>(cur, xq);
     long long q;

@@ -32,7 +32,7 @@ lsp_status mse_spec(const lsp_vol_s* v, const float* x, const float* y, int64_t 
                     float* dldf, float* dldx, double* loss, hipStream_t st);
 template <class SP>
 lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t n, const void* ws,
-                    float* const* grad_c, float* grad_x, hipStream_t st);
+                    float* const* grad_c, float* grad_x, hipStream_t st, bool g_saved);
 template <class SP>
 lsp_status sched_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes);
 template <class SP>

@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restri
     const float r = acc - y[q];
     const float dl = 2.f * r * inv_n;
     if (f) f[q] = acc;      // optional
-    dldf[q] = dl;
+    if (dldf) dldf[q] = dl;
     if constexpr (GRAD) {
 #pragma unroll
       for (int d = 0; d < SP::S; ++d) dldx[q * SP::S + d] = dl * gx[d];

@@ -41,6 +41,7 @@ struct Bin {
   size_t lds_adj_g;     // fixed-point gradient region alone
   bool adj_stage_c;
   size_t off_gmax;      // max |g| partials and result (the adjoint's fixed-point scale)
+  size_t off_gsave;     // dL/df of the last scheduled MSE forward (schedule order, or by query if split)
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -110,6 +111,7 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   bn.off_gpart = o; o = align256(o + (bn.split ? static_cast<size_t>(bn.at_size) * g.items * SP::S : 0));
   bn.off_priv = o; o = align256(o + (grad_lds <= kLdsMax ? 4ull * g.nunits * nc * bn.region : 0));
   bn.off_gmax = o; o = align256(o + 4ull * (kAbsMaxParts + 1));
+  bn.off_gsave = o; o = align256(o + 4ull * static_cast<size_t>(bn.split ? g.n : g.items));
   bn.bytes = o;
   return bn;
 }
@@ -150,12 +152,13 @@ lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT*
   const Rec<SP::S>* recs = reinterpret_cast<const Rec<SP::S>*>(base + bn.off_recs);
   constexpr bool SPLIT = SplitPolicy<SP>::value;
   const float inv_n = 1.0f / static_cast<float>(n);
+  float* gsave = MSE ? reinterpret_cast<float*>(const_cast<char*>(base) + bn.off_gsave) : nullptr;
   const dim3 grid(unit_grid(g.nunits * g.wpu));
   // the unit's coefficients are staged in LDS when the region fits
   constexpr int NT = SP::S == 3 ? 256 : 512;
 #define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                                 \
   hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT), bn.lds_eval, \
-                     st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss)
+                     st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave)
   if constexpr (SPLIT) {
     AT* fo = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_fpart);
     AT* go = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_gpart);
@@ -167,10 +170,10 @@ lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT*
     const dim3 cg(std::min(grid_of(n), 1024u));
     if (grad)
       hipLaunchKernelGGL((k_combine<SP, AT, true, MSE>), cg, dim3(256), 0, st, fo, go, static_cast<long long>(n), f,
-                         grad, y, inv_n, dldf, loss);
+                         grad, y, inv_n, dldf, loss, gsave);
     else
       hipLaunchKernelGGL((k_combine<SP, AT, false, MSE>), cg, dim3(256), 0, st, fo, go, static_cast<long long>(n), f,
-                         grad, y, inv_n, dldf, loss);
+                         grad, y, inv_n, dldf, loss, gsave);
   } else {
     AT* fo = f;
     AT* go = grad;
@@ -238,7 +241,7 @@ lsp_status mse_spec(const lsp_vol_s* v, const float* x, const float* y, int64_t 
 
 template <class SP, class CT>
 lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_t n, const void* ws,
-                      float* const* grad_c, float* grad_x, hipStream_t st) {
+                      float* const* grad_c, float* grad_x, hipStream_t st, bool g_saved) {
   GradVol gv{};
   for (int k = 0; k < SP::M; ++k) gv.base[k] = grad_c[k];
   if (!ws) {
@@ -252,6 +255,9 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   }
   const Bin bn = make_bin<SP>(v, n);
   const BinGeom& gm = bn.g;
+  // g_saved: the upstream gradient is the dL/df that the last scheduled MSE
+  // forward left in the workspace (schedule order unless coset-split)
+  if (g_saved) g = reinterpret_cast<const float*>(static_cast<const char*>(ws) + bn.off_gsave);
   // the gather pass: one block per 256-site run along axis 0 of each row of
   // the other axes, per coset
   const unsigned segs = grid_of(v->vol.dims[0]);
@@ -260,6 +266,7 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   if (bn.lds_adj_g > kLdsMax || rows * segs > 0x7fffffffull) {
     // a unit's region does not fit in LDS (large 4-D bricks): scatter-add
     // with global atomics in the given order
+    if (g_saved) return LSP_ERR_UNSUPPORTED;
     if (grad_x)
       hipLaunchKernelGGL((k_adjoint<SP, CT, true, false>), dim3(grid_of(n)), dim3(256), 0, st, v->vol, gv, x, g,
                          static_cast<long long>(n), nullptr, grad_x);
@@ -277,6 +284,7 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   if constexpr (SPLIT) gx_out = reinterpret_cast<float*>(const_cast<char*>(base) + bn.off_gpart);
   const dim3 grid(unit_grid(gm.nunits));
   const size_t lds_g = bn.lds_adj_g;
+  const int gsorted = (g_saved && !SPLIT) ? 1 : 0;
   // max |g|: the power-of-two scale of the fixed-point regions
   unsigned* gparts = reinterpret_cast<unsigned*>(const_cast<char*>(base) + bn.off_gmax);
   unsigned* gmax = gparts + kAbsMaxParts;
@@ -286,13 +294,13 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   if (grad_x) {
     if (bn.adj_stage_c)
       hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, true>), grid, dim3(512), bn.lds_adj, st, v->vol, gv,
-                         gm, recs, start, g, gx_out, priv, gmax);
+                         gm, recs, start, g, gx_out, priv, gmax, gsorted);
     else
       hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
-                         recs, start, g, gx_out, priv, gmax);
+                         recs, start, g, gx_out, priv, gmax, gsorted);
   } else {
     hipLaunchKernelGGL((k_adjoint_binned<SP, CT, false, SPLIT, false>), grid, dim3(512), lds_g, st, v->vol, gv, gm,
-                       recs, start, g, gx_out, priv, gmax);
+                       recs, start, g, gx_out, priv, gmax, gsorted);
   }
   const unsigned rpb = v->vol.dims[0] >= 256 ? 1u : 256u / static_cast<unsigned>(v->vol.dims[0]);
   const unsigned blocks = static_cast<unsigned>((rows + rpb - 1) / rpb) * segs;
@@ -306,11 +314,11 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
 
 template <class SP>
 lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t n, const void* ws,
-                    float* const* grad_c, float* grad_x, hipStream_t st) {
+                    float* const* grad_c, float* grad_x, hipStream_t st, bool g_saved) {
   switch (v->dtype) {
-    case LSP_F32: return launch_adj<SP, float>(v, x, g, n, ws, grad_c, grad_x, st);
-    case LSP_BF16: return launch_adj<SP, bf16_t>(v, x, g, n, ws, grad_c, grad_x, st);
-    case LSP_F16: return launch_adj<SP, f16_t>(v, x, g, n, ws, grad_c, grad_x, st);
+    case LSP_F32: return launch_adj<SP, float>(v, x, g, n, ws, grad_c, grad_x, st, g_saved);
+    case LSP_BF16: return launch_adj<SP, bf16_t>(v, x, g, n, ws, grad_c, grad_x, st, g_saved);
+    case LSP_F16: return launch_adj<SP, f16_t>(v, x, g, n, ws, grad_c, grad_x, st, g_saved);
   }
   return LSP_ERR_DTYPE;
 }
@@ -387,7 +395,7 @@ lsp_status render_spec(const lsp_vol_s* v, const RayParams& rp, const RenderPara
   template lsp_status mse_spec<SP>(const lsp_vol_s*, const float*, const float*, int64_t, const void*, float*,   \
                                    float*, float*, double*, hipStream_t);                                       \
   template lsp_status adj_spec<SP>(const lsp_vol_s*, const float*, const float*, int64_t, const void*,           \
-                                   float* const*, float*, hipStream_t);                                         \
+                                   float* const*, float*, hipStream_t, bool);                                   \
   template lsp_status sched_size_spec<SP>(const lsp_vol_s*, int64_t, size_t*);                                  \
   template lsp_status sched_spec<SP>(const lsp_vol_s*, const float*, int64_t, void*, hipStream_t);               \
   template lsp_status rays_spec<SP>(const lsp_vol_s*, const RayParams&, int64_t, int64_t, float*, float*,        \

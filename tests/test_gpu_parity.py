@@ -441,3 +441,28 @@ def test_scheduled_edge_cases(lsp, name):
         assert float((a - b).abs().max()) <= 1e-6 * max(1.0, float(b.abs().max()))
     assert bool(torch.isnan(gxm[len(X) + 2:]).all())
     assert float((gxm[: len(X) + 2] - gxf).abs().max()) <= 1e-6 * max(1.0, float(gxf.abs().max()))
+
+
+@pytest.mark.parametrize("name", ["c4", "c5", "d4"])
+def test_mse_backward_fused(lsp, name):
+    """The fused MSE backward (dL/df kept in the workspace by the scheduled
+    forward) equals the scheduled adjoint fed the returned dL/df, also when
+    the forward stores neither f nor dL/df."""
+    torch = _torch()
+    cfg, coeffs, X = small_case(name, seed=41)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    x = torch.from_numpy(X).cuda()
+    y = torch.from_numpy(I.targets(cfg, X)).cuda()
+    sch = sp.schedule(vol, x)
+    _, dldf, loss = sp.eval_mse(vol, x, y, schedule=sch)
+    want, _ = sp.adjoint(vol, x, dldf, schedule=sch)
+    got = sp.mse_backward(vol, x, sch)
+    for a, b in zip(got, want):
+        assert float((a - b).abs().max()) <= 1e-6 * max(1e-12, float(b.abs().max()))
+    f2, d2, loss2, dx2 = sp.eval_mse(vol, x, y, schedule=sch, grad_x=True, want_f=False, want_dldf=False)
+    assert f2 is None and d2 is None
+    assert abs(float(loss2.item()) - float(loss.item())) <= 1e-12 * max(1.0, abs(float(loss.item())))
+    got2 = sp.mse_backward(vol, x, sch)
+    for a, b in zip(got2, want):
+        assert float((a - b).abs().max()) <= 1e-6 * max(1e-12, float(b.abs().max()))
