@@ -131,3 +131,26 @@ def test_schedule_workspace_checks():
         L.lsp_schedule_size(p, v, 1 << 31)          # items would overflow 32 bits
     L.lsp_vol_release(v)
     L.lsp_plan_destroy(p)
+
+
+def test_no_fallback_without_the_library(monkeypatch, tmp_path):
+    """The product path raises when the HIP library is absent; nothing falls
+    back to a CPU evaluation."""
+    L = _lib()
+    from paper_2102_08514_amd import api
+    cfg = W.get("c2")
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "liblsp.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        api.LatticeSpline(cfg.L, cfg.Xi)
+
+
+def test_host_tensors_are_rejected():
+    """Coefficients and queries must be device tensors: the API never
+    evaluates host memory."""
+    import torch
+    from paper_2102_08514_amd import api
+    cfg = W.get("c2")
+    sp = api.LatticeSpline(cfg.L, cfg.Xi)
+    with pytest.raises(ValueError, match="GPU"):
+        sp.bind([torch.zeros(8, 8, 8)])
