@@ -275,6 +275,47 @@ def test_full_size_sampled_c2(lsp):
     want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
     assert normwise(f[idx], want, coeffs) <= 1e-5
     assert np.all(np.isfinite(f))
+    # the benchmark's sorted launch: same arithmetic per query (one sub-region), so the same bits
+    x = torch.from_numpy(X).cuda()
+    fs = sp.eval(vol, x, schedule=sp.schedule(vol, x)).cpu().numpy()
+    assert np.array_equal(fs, f)
+
+
+def test_mse_step_full_size_c4(lsp):
+    """The benchmark's c4 training step at full size (4 x 128^3, 2^22 queries):
+    scheduled MSE forward storing neither f nor dL/df, then the fused
+    backward.  The loss matches the one computed from f in FP64, sampled f
+    matches the oracle, dL/dx matches the gradient path, and dL/dc matches
+    the given-order adjoint fed dL/df = 2 (f - y) / n."""
+    torch = _torch()
+    cfg = W.get("c4")
+    coeffs = I.coefficients(cfg)
+    X = I.queries(cfg)
+    n = len(X)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    dev = to_dev(coeffs, torch.float32)
+    vol = sp.bind(dev)
+    x = torch.from_numpy(X).cuda()
+    y = torch.from_numpy(I.targets(cfg, X)).cuda()
+    sch = sp.schedule(vol, x)
+    f_none, d_none, loss, dldx = sp.eval_mse(vol, x, y, schedule=sch, grad_x=True, want_f=False,
+                                             want_dldf=False)
+    assert f_none is None and d_none is None
+    gc = sp.mse_backward(vol, x, sch)
+    f, gf = sp.eval(vol, x, grad=True)
+    r = f.double() - y.double()
+    want_loss = float((r * r).mean())
+    assert abs(float(loss.item()) - want_loss) <= 1e-5 * want_loss
+    idx = np.random.default_rng(42).choice(n, 256, replace=False)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
+    assert normwise(f.cpu().numpy()[idx], want, coeffs) <= 1e-5
+    want_dx = (2.0 / n) * r[:, None] * gf.double()
+    assert float((dldx.double() - want_dx).abs().max()) <= 1e-5 * float(want_dx.abs().max())
+    g = (2.0 / n * r).float()
+    ga, _ = sp.adjoint(vol, x, g)
+    for a, b in zip(gc, ga):
+        assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max())
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"] + TABLE1)
