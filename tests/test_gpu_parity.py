@@ -236,6 +236,30 @@ def test_rays_against_oracle(lsp):
     np.testing.assert_allclose(out[:, 1:], gw.reshape(nrays, S, 3).sum(1), atol=S * 1e-4)
 
 
+def test_rays_full_size_sampled_c3(lsp):
+    """c3's full launch (2 x 192^3, 1024 x 1024 rays, 512 steps, forward and
+    gradient summed per ray), checked on sampled rays: every sample of those
+    rays is evaluated by the oracle at the same float32 positions."""
+    torch = _torch()
+    cfg = W.get("c3")
+    coeffs = I.coefficients(cfg)
+    Wd, Hd = cfg.extra["rays"]
+    S = cfg.extra["steps"]
+    c, A = I.ray_params(cfg)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    out = sp.rays(vol, c.astype(np.float32), A.astype(np.float32), Wd, Hd, S).cpu().numpy()
+    assert out.shape == (Wd * Hd, 4) and np.all(np.isfinite(out))
+    rays = np.concatenate([[0, Wd * Hd - 1], np.random.default_rng(43).choice(Wd * Hd, 4, replace=False)])
+    P = I.ray_samples(cfg, _tile_pixels(rays, Wd)[:, None], np.arange(S)[None, :], W=Wd, H=Hd, S=S)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    fw, gw = o.eval([a.astype(np.float32).astype(np.float64) for a in coeffs], P.reshape(-1, 3).astype(np.float64),
+                    want_grad=True)
+    cmax = max(float(np.abs(a).max()) for a in coeffs)
+    np.testing.assert_allclose(out[rays, 0], fw.reshape(len(rays), S).sum(1), rtol=0, atol=S * 1e-5 * cmax)
+    np.testing.assert_allclose(out[rays, 1:], gw.reshape(len(rays), S, 3).sum(1), rtol=0, atol=S * 1e-4 * cmax)
+
+
 def test_edge_cases(lsp):
     torch = _torch()
     cfg, coeffs, X = small_case("c2", n=300, seed=9)
