@@ -384,12 +384,14 @@ def test_scheduled_order(lsp, name):
         assert abs(float(la) - float(lb)) <= 1e-6 * max(1.0, abs(float(la)))
 
 
-def test_scheduled_full_size_sampled(lsp):
-    """c5 at its full size through the schedule (the benchmark's launch), on
-    sampled outputs against the oracle; the adjoint's total mass is checked
-    against the forward by the adjoint identity <A c, g> = <c, A^T g>."""
+@pytest.mark.parametrize("name,samples", [("c5", 512), ("d4", 128)])
+def test_scheduled_full_size_sampled(lsp, name, samples):
+    """c5 (2 x 48^4) and the D4 spline of Sec. 5.2 (8 x 24^4), 2^22 queries
+    each, through the schedule (the benchmark's launch), on sampled outputs
+    against the oracle; the adjoint's total mass is checked against the
+    forward by the adjoint identity <A c, g> = <c, A^T g>."""
     torch = _torch()
-    cfg = W.get("c5")
+    cfg = W.get(name)
     coeffs = I.coefficients(cfg)
     X = I.queries(cfg)
     sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
@@ -398,7 +400,7 @@ def test_scheduled_full_size_sampled(lsp):
     x = torch.from_numpy(X).cuda()
     sch = sp.schedule(vol, x)
     f = sp.eval(vol, x, schedule=sch)
-    idx = np.random.default_rng(14).choice(len(X), 512, replace=False)
+    idx = np.random.default_rng(14).choice(len(X), samples, replace=False)
     o = ConvolutionSumOracle(cfg.L, cfg.Xi)
     want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
     assert normwise(f.cpu().numpy()[idx], want, coeffs) <= 1e-5
