@@ -91,6 +91,24 @@ def test_forward_fp64_check(lsp, name):
     assert err <= 1e-11
 
 
+def test_c1_full_workload_fp64(lsp):
+    """c1 in full (2 x 32^3 FP64 coefficients, 10^5 queries), in given order
+    and through the schedule, every query against the oracle."""
+    torch = _torch()
+    cfg = W.get("c1")
+    coeffs = I.coefficients(cfg)
+    X = I.queries(cfg)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval([c.astype(np.float64) for c in coeffs], X.astype(np.float64))
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float64))
+    x = torch.from_numpy(X).cuda()
+    for sch in (None, sp.schedule(vol, x)):
+        f = sp.eval(vol, x, schedule=sch)
+        assert f.dtype == torch.float64
+        assert normwise(f.cpu().numpy(), want, coeffs) <= 1e-11
+
+
 @pytest.mark.parametrize("name,dt", [("c2", "bf16"), ("c3", "bf16"), ("c5", "bf16"), ("c3", "f16")])
 def test_forward_low_precision_storage(lsp, name, dt):
     torch = _torch()
