@@ -319,8 +319,14 @@ def test_full_size_sampled_c2(lsp):
     assert np.all(np.isfinite(f))
     # the benchmark's sorted launch: same arithmetic per query (one sub-region), so the same bits
     x = torch.from_numpy(X).cuda()
-    fs = sp.eval(vol, x, schedule=sp.schedule(vol, x)).cpu().numpy()
+    sch = sp.schedule(vol, x)
+    fs = sp.eval(vol, x, schedule=sch).cpu().numpy()
     assert np.array_equal(fs, f)
+    # BF16 storage (the benchmark's --dtype bf16 line) against the oracle on the rounded coefficients
+    dev = to_dev(coeffs, torch.bfloat16)
+    rounded = [d.float().cpu().numpy().astype(np.float64) for d in dev]
+    fb = sp.eval(sp.bind(dev), x, schedule=sch).cpu().numpy()
+    assert normwise(fb[idx], o.eval(rounded, X[idx].astype(np.float64)), coeffs) <= 1e-5
 
 
 def test_mse_step_full_size_c4(lsp):
