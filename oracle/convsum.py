@@ -163,6 +163,31 @@ class ConvolutionSumOracle:
                 out[k] += np.bincount(flat[sel], weights=contrib[sel], minlength=size)
         return [o.reshape(tuple(reversed(dims))) for o in out]
 
+    def adjoint_at(self, X, gout, sites):
+        """The transpose of c -> f at chosen sites only.  For every (k, i) in
+        ``sites`` (coset k, array index i as an s-tuple) returns
+        sum_q g_q phi(x_q - m) with m = D i + l_k, summed over every query
+        whose x_q lies in the support of phi(. - m): the column of Eq.
+        conv_sum that belongs to c_m.  Queries are found by sorting them
+        along axis 0 once and keeping those inside the support's bounding
+        box around m; the rest is the plain definition."""
+        X = np.asarray(X, dtype=float).reshape(-1, self.s)
+        gout = np.asarray(gout, dtype=float).reshape(-1)
+        order = np.argsort(X[:, 0], kind="stable")
+        xs = X[order, 0]
+        out = np.zeros(len(sites))
+        for j, (k, idx) in enumerate(sites):
+            m = self.lat.D * np.asarray(idx, dtype=float) + np.asarray(self.lat.shifts[k], dtype=float)
+            lo = np.searchsorted(xs, m[0] - self.half[0], side="left")
+            hi = np.searchsorted(xs, m[0] + self.half[0], side="right")
+            cand = order[lo:hi]
+            W = X[cand] - m
+            keep = np.all(np.abs(W) <= self.half, axis=1)
+            cand, W = cand[keep], W[keep]
+            if len(cand):
+                out[j] = float(np.sum(gout[cand] * self.phi(W)))
+        return out
+
     def nonzero_count(self, X, dims):
         """Number of sites with phi(x - site) != 0 per query (Table 1's
         '# Lookups' reading: sites with nonzero weight)."""

@@ -24,6 +24,29 @@ def _require_device(*ts):
             raise ValueError("tensors must be contiguous")
 
 
+def _check_queries(x, s):
+    """x must be an N x s float32 tensor (row-major; the device is checked
+    after every shape and dtype check of a call)."""
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != s:
+        raise ValueError(f"x must be an N x {s} float32 tensor")
+
+
+def _check_grad_c(grad_c, vol):
+    """grad_c: one float32 array per coset, shaped like the coefficient arrays."""
+    if len(grad_c) != len(vol.coeffs):
+        raise ValueError(f"grad_c must hold {len(vol.coeffs)} arrays (one per coset)")
+    for t, c in zip(grad_c, vol.coeffs):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.shape != c.shape:
+            raise ValueError("grad_c arrays must be float32 and shaped like the coefficient arrays")
+    _require_device(*grad_c)
+
+
+def _check_per_query(v, n, name):
+    """v must be a float32 vector of one value per query."""
+    if not isinstance(v, torch.Tensor) or v.dtype != torch.float32 or v.dim() != 1 or v.shape[0] != n:
+        raise ValueError(f"{name} must be a float32 vector of length {n} (one value per query)")
+
+
 class Volume:
     """Coefficient arrays bound to a plan: M device tensors of shape
     (n_{s-1}, ..., n_0) (x fastest), one per coset, same dtype."""
@@ -59,11 +82,16 @@ class Volume:
 
 
 class Schedule:
-    """Evaluation order for one batch of queries (device workspace)."""
+    """Evaluation order for one batch of queries (device workspace).  It is
+    valid only for the same queries x and a volume of the same dims and
+    dtype class as the one it was built with."""
 
     def __init__(self, spline, vol, x):
+        _check_queries(x, spline.s)
         _require_device(x)
         self.n = x.shape[0]
+        self.dims = vol.dims
+        self.wide = vol.dtype == torch.float64
         self.bytes = L.lsp_schedule_size(spline.plan, vol.handle, self.n)
         # 256-byte aligned: torch's caching allocator returns 512-byte aligned blocks
         self.ws = torch.empty(max(self.bytes, 1), dtype=torch.uint8, device=x.device)
@@ -97,9 +125,8 @@ class LatticeSpline:
 
     # ------------------------------------------------------------- forward
     def eval(self, vol, x, grad=False, out=None, grad_out=None, schedule=None):
+        _check_queries(x, self.s)
         _require_device(x)
-        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[1] != self.s:
-            raise ValueError("x must be an N x s float32 tensor")
         n = x.shape[0]
         f = out if out is not None else torch.empty(n, device=x.device, dtype=vol.out_dtype)
         g = None
@@ -108,22 +135,26 @@ class LatticeSpline:
         if schedule is None:
             L.lsp_eval(self.plan, vol.handle, x.data_ptr(), n, f.data_ptr(), _ptr(g), _stream())
         else:
-            self._check_sched(schedule, x)
+            self._check_sched(schedule, x, vol)
             L.lsp_eval_scheduled(self.plan, vol.handle, x.data_ptr(), n, schedule.ws.data_ptr(), schedule.bytes,
                                  f.data_ptr(), _ptr(g), _stream())
         return (f, g) if grad else f
 
     @staticmethod
-    def _check_sched(schedule, x):
+    def _check_sched(schedule, x, vol):
         if schedule.n != x.shape[0] or schedule.x.data_ptr() != x.data_ptr():
             raise ValueError("the schedule was built for other queries")
+        if schedule.dims != vol.dims or schedule.wide != (vol.dtype == torch.float64):
+            raise ValueError("the schedule was built for a volume of other dims or dtype class")
 
     def eval_mse(self, vol, x, y, schedule=None, grad_x=False, want_f=True, want_dldf=True):
         """f, dL/df, L (and dL/dx if grad_x) for L = mean (f - y)^2; f (dL/df)
         is None when want_f (want_dldf) is False.  With a schedule, dL/df also
         stays in the schedule's workspace for mse_backward."""
-        _require_device(x, y)
+        _check_queries(x, self.s)
         n = x.shape[0]
+        _check_per_query(y, n, "y")
+        _require_device(x, y)
         f = torch.empty(n, device=x.device, dtype=torch.float32) if want_f else None
         dldf = torch.empty(n, device=x.device, dtype=torch.float32) if want_dldf else None
         dldx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
@@ -132,7 +163,7 @@ class LatticeSpline:
             L.lsp_eval_mse(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, _ptr(f), _ptr(dldf),
                            _ptr(dldx), loss.data_ptr(), _stream())
         else:
-            self._check_sched(schedule, x)
+            self._check_sched(schedule, x, vol)
             L.lsp_eval_mse_scheduled(self.plan, vol.handle, x.data_ptr(), y.data_ptr(), n, schedule.ws.data_ptr(),
                                      schedule.bytes, _ptr(f), _ptr(dldf), _ptr(dldx), loss.data_ptr(),
                                      _stream())
@@ -142,26 +173,31 @@ class LatticeSpline:
         """grad_c (zero-initialised here unless given) += A^T dL/df, with the
         dL/df that the preceding eval_mse(schedule=schedule) left in the
         schedule's workspace."""
+        _check_queries(x, self.s)
         _require_device(x)
-        self._check_sched(schedule, x)
+        self._check_sched(schedule, x, vol)
         if grad_c is None:
             grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
+        _check_grad_c(grad_c, vol)
         L.lsp_mse_backward_scheduled(self.plan, vol.handle, x.data_ptr(), x.shape[0], schedule.ws.data_ptr(),
                                      schedule.bytes, [t.data_ptr() for t in grad_c], _stream())
         return grad_c
 
     def adjoint(self, vol, x, g, grad_x=False, grad_c=None, schedule=None):
         """grad_c (zero-initialised here unless given) += A^T g; grad_x = g * grad f."""
-        _require_device(x, g)
+        _check_queries(x, self.s)
         n = x.shape[0]
+        _check_per_query(g, n, "g")
+        _require_device(x, g)
         if grad_c is None:
             grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
+        _check_grad_c(grad_c, vol)
         gx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
         if schedule is None:
             L.lsp_eval_adjoint(self.plan, vol.handle, x.data_ptr(), g.data_ptr(), n, [t.data_ptr() for t in grad_c],
                                _ptr(gx), _stream())
         else:
-            self._check_sched(schedule, x)
+            self._check_sched(schedule, x, vol)
             L.lsp_eval_adjoint_scheduled(self.plan, vol.handle, x.data_ptr(), g.data_ptr(), n,
                                          schedule.ws.data_ptr(), schedule.bytes, [t.data_ptr() for t in grad_c],
                                          _ptr(gx), _stream())

@@ -8,7 +8,9 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "lsp_internal.h"
@@ -117,6 +119,64 @@ std::vector<int> canon_dir(std::vector<int> v) {
   std::vector<int> neg(v.size());
   for (size_t i = 0; i < v.size(); ++i) neg[i] = -v[i];
   return std::max(v, neg);
+}
+
+// Launch limits of the given-order kernels: one work item per lane in a 1-D
+// grid whose global size must stay below 2^32.
+constexpr int64_t kMaxQueries = int64_t(1) << 31;
+
+// What a schedule workspace was filled for.  The workspace layout (key
+// histograms, record offsets, partial buffers) depends on the plan, the
+// volume dims, the dtype class and n, and the records hold the queries x;
+// the scheduled calls refuse a workspace that lsp_schedule filled for
+// anything else.  Keyed by workspace address; bounded.
+struct SchedKey {
+  int spec;
+  int dims[kMaxDim];
+  int wide;            // FP64 volume (8-byte partials) or not
+  const float* x;
+  int64_t n;
+  bool operator==(const SchedKey& o) const {
+    for (int d = 0; d < kMaxDim; ++d)
+      if (dims[d] != o.dims[d]) return false;
+    return spec == o.spec && wide == o.wide && x == o.x && n == o.n;
+  }
+};
+
+std::mutex g_sched_mu;
+std::unordered_map<const void*, SchedKey>& sched_registry() {
+  static std::unordered_map<const void*, SchedKey> reg;
+  return reg;
+}
+constexpr size_t kMaxSchedRecords = 1 << 16;
+
+SchedKey sched_key(lsp_plan plan, lsp_vol vol, const float* x, int64_t n) {
+  SchedKey k{};
+  k.spec = plan->spec;
+  for (int d = 0; d < kMaxDim; ++d) k.dims[d] = vol->vol.dims[d];
+  k.wide = vol->dtype == LSP_F64 ? 1 : 0;
+  k.x = x;
+  k.n = n;
+  return k;
+}
+
+void sched_record(const void* ws, const SchedKey& k) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  auto& reg = sched_registry();
+  if (reg.size() >= kMaxSchedRecords && reg.find(ws) == reg.end()) reg.clear();
+  reg[ws] = k;
+}
+
+void sched_forget(const void* ws) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  sched_registry().erase(ws);
+}
+
+bool sched_matches(const void* ws, const SchedKey& k) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  auto& reg = sched_registry();
+  auto it = reg.find(ws);
+  return it != reg.end() && it->second == k;
 }
 
 #define LSP_DISPATCH(spec, FN, ...)                                   \
@@ -303,7 +363,7 @@ lsp_status lsp_eval(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void*
   if (n < 0) return LSP_ERR_INVALID;
   if (n == 0) return LSP_OK;
   if (!x || !f) return LSP_ERR_NULL;
-  if (n > (int64_t(1) << 40)) return LSP_ERR_INVALID;
+  if (n > kMaxQueries) return LSP_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, eval_spec, vol, x, n, nullptr, f, grad_x, s)
 }
@@ -316,6 +376,7 @@ lsp_status lsp_eval_mse(lsp_plan plan, lsp_vol vol, const float* x, const float*
   if (n == 0) return LSP_OK;
   if (!x || !y || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  if (n > kMaxQueries) return LSP_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, mse_spec, vol, x, y, n, nullptr, f, dloss_df, dloss_dx, loss, s)
 }
@@ -331,6 +392,7 @@ lsp_status lsp_eval_adjoint(lsp_plan plan, lsp_vol vol, const float* x, const fl
   for (int k = 0; k < sd.M; ++k)
     if (!grad_c[k]) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
+  if (n > kMaxQueries) return LSP_ERR_INVALID;
   hipStream_t s = static_cast<hipStream_t>(stream);
   LSP_DISPATCH(plan->spec, adj_spec, vol, x, g, n, nullptr, grad_c, grad_x, s, false)
 }
@@ -341,7 +403,7 @@ lsp_status lsp_eval_rays(lsp_plan plan, lsp_vol vol, const float* c, const float
   if (st != LSP_OK) return st;
   if (!c || !A) return LSP_ERR_NULL;
   if (W <= 0 || H <= 0 || (W & 7) || (H & 7) || steps <= 0 || ray0 < 0 || nrays < 0 ||
-      ray0 + nrays > static_cast<int64_t>(W) * H)
+      ray0 + nrays > static_cast<int64_t>(W) * H || nrays > kMaxQueries)
     return LSP_ERR_INVALID;
   if (nrays == 0) return LSP_OK;
   if (!out) return LSP_ERR_NULL;
@@ -361,7 +423,7 @@ lsp_status lsp_render(lsp_plan plan, lsp_vol vol, const float* c, const float* A
   if (st != LSP_OK) return st;
   if (!c || !A || !params) return LSP_ERR_NULL;
   if (W <= 0 || H <= 0 || (W & 7) || (H & 7) || steps <= 0 || ray0 < 0 || nrays < 0 ||
-      ray0 + nrays > static_cast<int64_t>(W) * H)
+      ray0 + nrays > static_cast<int64_t>(W) * H || nrays > kMaxQueries)
     return LSP_ERR_INVALID;
   const lsp_render_params& p = *params;
   if (p.tf_len < 2 || !(p.f1 > p.f0) || !(p.grad_eps >= 0.f)) return LSP_ERR_INVALID;
@@ -389,6 +451,15 @@ static lsp_status check_ws(lsp_plan plan, lsp_vol vol, int64_t n, const void* ws
   return ws_bytes >= need ? LSP_OK : LSP_ERR_INVALID;
 }
 
+// a *_scheduled call: the workspace must hold a schedule of these queries for
+// this plan and a volume of the same dims and dtype class
+static lsp_status check_sched(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* ws,
+                              size_t ws_bytes) {
+  lsp_status st = check_ws(plan, vol, n, ws, ws_bytes);
+  if (st != LSP_OK) return st;
+  return sched_matches(ws, sched_key(plan, vol, x, n)) ? LSP_OK : LSP_ERR_INVALID;
+}
+
 lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes) {
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
@@ -397,16 +468,23 @@ lsp_status lsp_schedule_size(lsp_plan plan, lsp_vol vol, int64_t n, size_t* byte
   LSP_DISPATCH(plan->spec, sched_size_spec, vol, n, bytes)
 }
 
+static lsp_status dispatch_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace,
+                                    hipStream_t s) {
+  LSP_DISPATCH(plan->spec, sched_spec, vol, x, n, workspace, s)
+}
+
 lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* workspace, size_t ws_bytes,
                         void* stream) {
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
   if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
-  if (n == 0) return LSP_OK;
-  if (!x) return LSP_ERR_NULL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  LSP_DISPATCH(plan->spec, sched_spec, vol, x, n, workspace, s)
+  if (n > 0 && !x) return LSP_ERR_NULL;
+  sched_forget(workspace);
+  if (n > 0 && (st = dispatch_schedule(plan, vol, x, n, workspace, static_cast<hipStream_t>(stream))) != LSP_OK)
+    return st;
+  sched_record(workspace, sched_key(plan, vol, x, n));
+  return LSP_OK;
 }
 
 lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
@@ -414,7 +492,7 @@ lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
-  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if ((st = check_sched(plan, vol, x, n, workspace, ws_bytes)) != LSP_OK) return st;
   if (n == 0) return LSP_OK;
   if (!x || !f) return LSP_ERR_NULL;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -427,7 +505,7 @@ lsp_status lsp_eval_mse_scheduled(lsp_plan plan, lsp_vol vol, const float* x, co
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
-  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if ((st = check_sched(plan, vol, x, n, workspace, ws_bytes)) != LSP_OK) return st;
   if (n == 0) return LSP_OK;
   if (!x || !y || !loss) return LSP_ERR_NULL;
   if (vol->dtype == LSP_F64) return LSP_ERR_DTYPE;
@@ -441,7 +519,7 @@ lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
-  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if ((st = check_sched(plan, vol, x, n, workspace, ws_bytes)) != LSP_OK) return st;
   if (n == 0) return LSP_OK;
   if (!x || !g || !grad_c) return LSP_ERR_NULL;
   const SpecDesc& sd = specs()[plan->spec];
@@ -457,7 +535,7 @@ lsp_status lsp_mse_backward_scheduled(lsp_plan plan, lsp_vol vol, const float* x
   lsp_status st = check_pv(plan, vol);
   if (st != LSP_OK) return st;
   if (n < 0) return LSP_ERR_INVALID;
-  if ((st = check_ws(plan, vol, n, workspace, ws_bytes)) != LSP_OK) return st;
+  if ((st = check_sched(plan, vol, x, n, workspace, ws_bytes)) != LSP_OK) return st;
   if (n == 0) return LSP_OK;
   if (!x || !grad_c) return LSP_ERR_NULL;
   const SpecDesc& sd = specs()[plan->spec];

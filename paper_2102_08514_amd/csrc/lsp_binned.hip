@@ -439,7 +439,7 @@ struct GatherLds {
 __device__ __forceinline__ long long to_fixed(float v) {
   const float hi = truncf(v * 0x1p-24f);
   const float lo = fmaf(hi, -0x1p24f, v);
-  return (static_cast<long long>(static_cast<int>(hi)) << 24) + static_cast<long long>(__float2int_rn(lo));
+  return static_cast<long long>(static_cast<int>(hi)) * (1ll << 24) + static_cast<long long>(__float2int_rn(lo));
 }
 
 // Scatter-add into an LDS region of 64-bit fixed-point accumulators: gs is
@@ -891,12 +891,13 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
 template <class SP>
 __global__ void __launch_bounds__(256) k_combine_gx(const float* __restrict__ gpart, long long n,
                                                     float* __restrict__ grad_x) {
-  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n * SP::S) return;
-  float s = 0.f;
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n * SP::S;
+       i += static_cast<long long>(gridDim.x) * blockDim.x) {
+    float s = 0.f;
 #pragma unroll
-  for (int k = 0; k < SP::M; ++k) s += gpart[k * n * SP::S + i];
-  grad_x[i] = s;
+    for (int k = 0; k < SP::M; ++k) s += gpart[k * n * SP::S + i];
+    grad_x[i] = s;
+  }
 }
 
 }  // namespace lsp

@@ -307,7 +307,7 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   hipLaunchKernelGGL((k_adjoint_gather<SP, SPLIT>), dim3(blocks, SP::M), dim3(256), 0, st, v->vol, gv, gm, start, priv,
                      segs, rpb, static_cast<unsigned>(rows));
   if (SPLIT && grad_x)
-    hipLaunchKernelGGL((k_combine_gx<SP>), dim3(grid_of(n * SP::S)), dim3(256), 0, st, gx_out,
+    hipLaunchKernelGGL((k_combine_gx<SP>), dim3(fill_grid(n * SP::S)), dim3(256), 0, st, gx_out,
                        static_cast<long long>(n), grad_x);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }

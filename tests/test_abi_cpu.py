@@ -133,6 +133,84 @@ def test_schedule_workspace_checks():
     L.lsp_plan_destroy(p)
 
 
+def test_schedule_is_tied_to_its_volume_and_queries():
+    """A workspace serves only the plan, volume dims, dtype class, queries and
+    n that lsp_schedule filled it for; the scheduled calls refuse anything
+    else (their workspace layout depends on all of these)."""
+    L = _lib()
+    lib = L.lib()
+    cfg = W.get("c4")
+    p = L.lsp_plan_create(cfg.L, cfg.Xi)
+    fake = [0x1000 * (k + 1) for k in range(4)]
+    v = L.lsp_vol_bind(p, 0, fake, (16, 16, 16))
+    v_small = L.lsp_vol_bind(p, 0, fake, (8, 8, 8))
+    v_wide = L.lsp_vol_bind(p, 3, fake, (16, 16, 16))
+    ws = 0x200000
+    need = max(L.lsp_schedule_size(p, w, 0) for w in (v, v_small, v_wide))
+    # never scheduled: refused
+    assert lib.lsp_eval_scheduled(p, v, None, 0, ws + 256, need, 0x1000, None, None) == -2
+    # an empty batch is scheduled without touching the GPU
+    assert lib.lsp_schedule(p, v, None, 0, ws, need, None) == 0
+    assert lib.lsp_eval_scheduled(p, v, None, 0, ws, need, 0x1000, None, None) == 0
+    assert lib.lsp_eval_adjoint_scheduled(p, v, None, None, 0, ws, need, None, None, None) == 0
+    # other dims, other dtype class, other queries: refused
+    assert lib.lsp_eval_scheduled(p, v_small, None, 0, ws, need, 0x1000, None, None) == -2
+    assert lib.lsp_eval_scheduled(p, v_wide, None, 0, ws, need, 0x1000, None, None) == -2
+    assert lib.lsp_eval_scheduled(p, v, 0x4000, 0, ws, need, 0x1000, None, None) == -2
+    # the same dims in another binding of the same plan and dtype class is fine
+    v2 = L.lsp_vol_bind(p, 1, fake, (16, 16, 16))
+    assert lib.lsp_eval_scheduled(p, v2, None, 0, ws, need, 0x1000, None, None) == 0
+    for h in (v, v_small, v_wide, v2):
+        L.lsp_vol_release(h)
+    L.lsp_plan_destroy(p)
+
+
+def test_query_count_limit():
+    """Given-order launches are 1-D grids of one query per lane: more than
+    2^31 queries (or rays) are refused before any launch."""
+    L = _lib()
+    lib = L.lib()
+    cfg = W.get("c2")
+    p = L.lsp_plan_create(cfg.L, cfg.Xi)
+    v = L.lsp_vol_bind(p, 0, [0x1000], (8, 8, 8))
+    big = (1 << 31) + 1
+    assert lib.lsp_eval(p, v, 0x1000, big, 0x1000, None, None) == -2
+    assert lib.lsp_eval_mse(p, v, 0x1000, 0x1000, big, None, None, None, 0x1000, None) == -2
+    assert lib.lsp_eval_adjoint(p, v, 0x1000, 0x1000, big, (ctypes.c_void_p * 1)(0x1000), None, None) == -2
+    L.lsp_vol_release(v)
+    L.lsp_plan_destroy(p)
+
+
+def test_api_argument_validation():
+    """The Python layer checks dtype, rank and length of every per-query
+    argument before anything reaches the library (a float64 target or a
+    short gradient would otherwise be read as float32 or past its end)."""
+    import torch
+    from paper_2102_08514_amd import api
+    cfg = W.get("c4")
+    sp = api.LatticeSpline(cfg.L, cfg.Xi)
+    x64 = torch.zeros(10, 3, dtype=torch.float64)
+    x2 = torch.zeros(10, 2)
+    x = torch.zeros(10, 3)
+    for bad in (x64, x2, torch.zeros(10)):
+        with pytest.raises(ValueError, match="x must be"):
+            sp.eval(None, bad)
+        with pytest.raises(ValueError, match="x must be"):
+            sp.eval_mse(None, bad, torch.zeros(10))
+        with pytest.raises(ValueError, match="x must be"):
+            sp.adjoint(None, bad, torch.zeros(10))
+    for bad in (torch.zeros(10, dtype=torch.float64), torch.zeros(9), torch.zeros(10, 1)):
+        with pytest.raises(ValueError, match="y must be"):
+            sp.eval_mse(None, x, bad)
+        with pytest.raises(ValueError, match="g must be"):
+            sp.adjoint(None, x, bad)
+    # correct shapes and dtypes, but host memory: refused as well
+    with pytest.raises(ValueError, match="GPU"):
+        sp.eval(None, x)
+    with pytest.raises(ValueError, match="GPU"):
+        sp.eval_mse(None, x, torch.zeros(10))
+
+
 def test_no_fallback_without_the_library(monkeypatch, tmp_path):
     """The product path raises when the HIP library is absent; nothing falls
     back to a CPU evaluation."""

@@ -15,7 +15,10 @@ from workloads.d4 import gaussian, prefilter_samples, study_grid
 pytestmark = pytest.mark.gpu
 
 CFG = W.get("d4")
-LEVELS = (1 / 16, 1 / 32, 1 / 64, 1 / 128)
+# the study starts at h = 1/2 and halves; the levels beyond 1/128 would need
+# 8 x 519^4 FP64 coefficients and more (about 4.6 TB), far beyond one GPU
+LEVELS = (1 / 2, 1 / 4, 1 / 8, 1 / 16, 1 / 32, 1 / 64, 1 / 128)
+COARSE = 3          # h = 1/2, 1/4: the Gaussian (sigma 1/8) is not yet resolved
 
 
 def _level(lsp, torch, h, Xw):
@@ -59,6 +62,9 @@ def test_d4_fourth_order_convergence(lsp):
         torch.cuda.empty_cache()
     ratios = [a / b for a, b in zip(errs, errs[1:])]
     print("ratios", ratios, flush=True)
-    assert all(r > 1.0 for r in ratios)
+    # from h = 1/8 on the error falls at every halving
+    assert all(r > 1.0 for r in ratios[COARSE - 1:])
+    # h = 1/2 is the coarsest level: no finer level may do worse
+    assert max(errs[1:]) < errs[0]
     # fourth order: error / 16 per halving (log2 ratio 4) in the asymptotic range
     assert 3.5 <= np.log2(ratios[-1]) <= 4.5

@@ -18,11 +18,8 @@ from workloads import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 10, 10), "c5": (7, 7, 7, 7),
-         "d4": (8, 8, 8, 8), "cc_tp2": (20, 20, 20), "cc_tp3": (20, 20, 20), "cc_tp4": (20, 20, 20),
-         "cc_linear_rd": (20, 20, 20), "bcc_quintic_rd": (12, 12, 12)}
-NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601, "d4": 401, "cc_tp2": 1301, "cc_tp3": 1301,
-      "cc_tp4": 96, "cc_linear_rd": 1301, "bcc_quintic_rd": 1301}   # cc_tp4: 12 directions make the oracle slow
+from gpu_cases import NQ, SMALL, normwise, small_case, tile_pixels, to_dev
+
 TABLE1 = ["cc_tp2", "cc_tp3", "cc_tp4", "cc_linear_rd", "bcc_quintic_rd"]
 C0_SPLINES = ("c1", "cc_tp2", "cc_linear_rd")   # linear pieces
 
@@ -30,34 +27,6 @@ C0_SPLINES = ("c1", "cc_tp2", "cc_linear_rd")   # linear pieces
 def _torch():
     import torch
     return torch
-
-
-def small_case(name, n=None, seed=0):
-    cfg = W.get(name)
-    dims = SMALL[name]
-    rng = np.random.default_rng(1000 + seed)
-    coeffs = [rng.uniform(-1, 1, tuple(reversed(dims))) for _ in range(cfg.M)]
-    n = NQ[name] if n is None else n
-    ext = cfg.D * (dims[0] - 1) + 1
-    # mostly interior, some straddling the border (zero extension), a few outside
-    X = rng.uniform(-2.0, ext + 1.0, (n, cfg.s))
-    X[: n // 2] = rng.uniform(cfg.D * 2, ext - cfg.D * 2 - 1, (n // 2, cfg.s))
-    # lattice sites, half-integers and cell centres exactly
-    special = rng.integers(3, ext - 4, (48, cfg.s)).astype(float)
-    special[16:32] += 0.5
-    special[32:40] += rng.integers(0, 2, (8, cfg.s)) * 0.25
-    X[-48:] = special
-    return cfg, coeffs, X.astype(np.float32)
-
-
-def to_dev(arrs, dtype):
-    torch = _torch()
-    return [torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda() for a in arrs]
-
-
-def normwise(a, b, coeffs):
-    scale = max(float(np.max(np.abs(c))) for c in coeffs)
-    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)))) / scale
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5", "d4"] + TABLE1)
@@ -204,14 +173,6 @@ def test_autograd_backward_matches_adjoint(lsp):
         assert float(np.max(np.abs(c.grad.cpu().numpy() - w))) <= 1e-5 * bound + 1e-9
 
 
-def _tile_pixels(rays, W):
-    r = np.asarray(rays)
-    tile, within = r >> 6, r & 63
-    u = (tile % (W // 8)) * 8 + (within & 7)
-    v = (tile // (W // 8)) * 8 + (within >> 3)
-    return u + W * v
-
-
 def test_rays_against_oracle(lsp):
     torch = _torch()
     cfg = W.get("c3")
@@ -230,7 +191,7 @@ def test_rays_against_oracle(lsp):
     ray0, nrays = 5, 100
     out, smp = sp.rays(vol, centre.astype(np.float32), A, Wd, H, S, ray0=ray0, nrays=nrays, samples=True)
     rays = np.arange(ray0, ray0 + nrays)
-    pix = _tile_pixels(rays, Wd)
+    pix = tile_pixels(rays, Wd)
     # the same float32 sample positions, computed independently on the CPU
     c32, A32 = centre.astype(np.float32), A
     u = (pix % Wd).astype(np.float32)
@@ -269,7 +230,7 @@ def test_rays_full_size_sampled_c3(lsp):
     out = sp.rays(vol, c.astype(np.float32), A.astype(np.float32), Wd, Hd, S).cpu().numpy()
     assert out.shape == (Wd * Hd, 4) and np.all(np.isfinite(out))
     rays = np.concatenate([[0, Wd * Hd - 1], np.random.default_rng(43).choice(Wd * Hd, 4, replace=False)])
-    P = I.ray_samples(cfg, _tile_pixels(rays, Wd)[:, None], np.arange(S)[None, :], W=Wd, H=Hd, S=S)
+    P = I.ray_samples(cfg, tile_pixels(rays, Wd)[:, None], np.arange(S)[None, :], W=Wd, H=Hd, S=S)
     o = ConvolutionSumOracle(cfg.L, cfg.Xi)
     fw, gw = o.eval([a.astype(np.float32).astype(np.float64) for a in coeffs], P.reshape(-1, 3).astype(np.float64),
                     want_grad=True)

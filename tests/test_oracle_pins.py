@@ -359,3 +359,27 @@ def test_adjoint_identity(name):
     r = o.adjoint(X, g, dims)
     rhs = sum(np.sum(ci * ri) for ci, ri in zip(c, r))
     assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("name", ["c4", "c5"])
+def test_adjoint_at_sites_is_a_column_of_the_forward(name):
+    """adjoint_at enumerates queries per site (column-wise); its value at
+    site m must equal <A e_m, g>: the forward sum with the single unit
+    coefficient c_m = 1 (found row-wise, per query), dotted with g.  It must
+    also agree with the full adjoint at every sampled site."""
+    cfg = W.get(name)
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    dims = (6,) * cfg.s
+    rng = np.random.default_rng(17)
+    X = rng.uniform(-1, 2 * 6, (300, cfg.s))
+    g = rng.normal(size=len(X))
+    full = o.adjoint(X, g, dims)
+    sites = [(int(rng.integers(cfg.M)), tuple(int(v) for v in rng.integers(0, 6, cfg.s))) for _ in range(12)]
+    sites += [(0, (0,) * cfg.s), (cfg.M - 1, (5,) * cfg.s)]
+    got = o.adjoint_at(X, g, sites)
+    for (k, idx), v in zip(sites, got):
+        e = [np.zeros(tuple(reversed(dims))) for _ in range(cfg.M)]
+        e[k][tuple(reversed(idx))] = 1.0
+        want = float(np.dot(o.eval(e, X), g))
+        assert abs(v - want) <= 1e-12 * max(1.0, abs(want))
+        assert abs(v - full[k][tuple(reversed(idx))]) <= 1e-12 * max(1.0, abs(v))
