@@ -83,6 +83,14 @@ typedef struct {
   int32_t offset_min;       /* per-axis site offset range around the cell */
   int32_t offset_max;
   char name[32];            /* spline name */
+  /* operation counts of the generated polynomial code, per coset and query:
+   * fma_b[k] multiply-adds of b = A c (the piece's monomial coefficients from
+   * the gathered stencil) and fma_w[k] of the stencil weights w = A^T mono
+   * (adjoint), both after common-subexpression factoring, for sub-region k;
+   * grad_terms: multiply-adds of the gradient from b and the monomials */
+  int32_t fma_b[16];
+  int32_t fma_w[16];
+  int32_t grad_terms;
 } lsp_info;
 
 /* Create a plan for lattice L (s x s, row-major; columns generate the lattice)

@@ -28,7 +28,8 @@ class LspInfo(ctypes.Structure):
         ("n_subregions", ctypes.c_int32), ("n_planes", ctypes.c_int32), ("fold_even", ctypes.c_int32),
         ("stencil", ctypes.c_int32 * 16), ("lookups", ctypes.c_int32), ("n_monomials", ctypes.c_int32),
         ("nnz", ctypes.c_int32 * 16), ("offset_min", ctypes.c_int32), ("offset_max", ctypes.c_int32),
-        ("name", ctypes.c_char * 32),
+        ("name", ctypes.c_char * 32), ("fma_b", ctypes.c_int32 * 16), ("fma_w", ctypes.c_int32 * 16),
+        ("grad_terms", ctypes.c_int32),
     ]
 
 
@@ -120,6 +121,8 @@ def lsp_plan_info(plan):
         "stencil": [info.stencil[k] for k in range(K)], "lookups": info.lookups,
         "n_monomials": info.n_monomials, "nnz": [info.nnz[k] for k in range(K)],
         "offset_min": info.offset_min, "offset_max": info.offset_max,
+        "fma_b": [info.fma_b[k] for k in range(K)], "fma_w": [info.fma_w[k] for k in range(K)],
+        "grad_terms": info.grad_terms,
     }
 
 

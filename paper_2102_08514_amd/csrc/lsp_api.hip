@@ -29,8 +29,9 @@ struct SpecDesc {
   int s, ndir, D, M, det, deg, K, Q, fold_even, nmon, omin, omax;
   std::vector<std::vector<int>> dirs;
   std::vector<std::vector<int>> shifts;
-  std::vector<int> nsite, nnz;
+  std::vector<int> nsite, nnz, fma_b, fma_w;
   int lookups;
+  int grad_terms;
 };
 
 template <class SP>
@@ -42,7 +43,15 @@ SpecDesc describe(const char* name) {
   d.omin = SP::OMIN; d.omax = SP::OMAX;
   for (int j = 0; j < SP::NDIR; ++j) d.dirs.emplace_back(SP::XI[j], SP::XI[j] + SP::S);
   for (int k = 0; k < SP::M; ++k) d.shifts.emplace_back(SP::SHIFT[k], SP::SHIFT[k] + SP::S);
-  for (int k = 0; k < SP::K; ++k) { d.nsite.push_back(SP::NSITE[k]); d.nnz.push_back(SP::NNZ[k]); }
+  for (int k = 0; k < SP::K; ++k) {
+    d.nsite.push_back(SP::NSITE[k]);
+    d.nnz.push_back(SP::NNZ[k]);
+    d.fma_b.push_back(SP::FMA_B[k]);
+    d.fma_w.push_back(SP::FMA_W[k]);
+  }
+  d.grad_terms = 0;
+  for (int m = 0; m < SP::NMON; ++m)
+    for (int r = 0; r < SP::S; ++r) d.grad_terms += SP::MDER[m][r] >= 0 ? 1 : 0;
   return d;
 }
 
@@ -297,7 +306,13 @@ lsp_status lsp_plan_info(lsp_plan plan, lsp_info* out) {
   for (int k = 0; k < sd.M; ++k)
     for (int a = 0; a < sd.s; ++a) out->shifts[k][a] = sd.shifts[k][a];
   out->degree = sd.deg; out->n_subregions = sd.K; out->n_planes = sd.Q; out->fold_even = sd.fold_even;
-  for (int k = 0; k < sd.K && k < 16; ++k) { out->stencil[k] = sd.nsite[k]; out->nnz[k] = sd.nnz[k]; }
+  for (int k = 0; k < sd.K && k < 16; ++k) {
+    out->stencil[k] = sd.nsite[k];
+    out->nnz[k] = sd.nnz[k];
+    out->fma_b[k] = sd.fma_b[k];
+    out->fma_w[k] = sd.fma_w[k];
+  }
+  out->grad_terms = sd.grad_terms;
   // every query gathers the same total over its cosets when K = 1; report the
   // sub-region-averaged total otherwise
   long long tot = 0;
