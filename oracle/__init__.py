@@ -17,7 +17,10 @@ Lattice Samplings: Part I"):
   with phi = |det L| M_Xi(. + c0) centred at the origin (c0 = half the sum
   of the directions) so that phi has partition of unity on the lattice
   (the requirement stated in Sec. 4.1);
-* its spatial gradient and the adjoint (transpose) of the map c -> f.
+* its spatial gradient and the adjoint (transpose) of the map c -> f;
+* Voronoi splines V_n (Sec. 3): V_1 from its definition as the overlap
+  volume of the Voronoi cell with its translate, and any V_n through the
+  paper's expansion into shifted box splines (``voronoi.py``).
 
 Everything is FP64 (numpy); an exact mode in ``fractions.Fraction`` exists
 for single points.
@@ -26,3 +29,4 @@ for single points.
 from .boxspline import BoxSplineOracle  # noqa: F401
 from .lattice import CosetLattice  # noqa: F401
 from .convsum import ConvolutionSumOracle  # noqa: F401
+from .voronoi import VoronoiSumOracle  # noqa: F401

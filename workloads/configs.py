@@ -50,6 +50,17 @@ D4_SHIFTS = ((0, 0, 0, 0), (1, 1, 0, 0), (1, 0, 1, 0), (0, 1, 1, 0), (1, 0, 0, 1
              (1, 1, 1, 1))
 
 
+# Voronoi cells of the BCC and FCC lattices as zonotopes sum_j [-1/2, 1/2] g_j
+# with g_j = w_j / 2 (truncated octahedron: 6 generators; rhombic
+# dodecahedron: 4).  The oracle checks that each spans its lattice's cell.
+VORONOI_SIGMA = 2
+VORONOI_GEN = {
+    "BCC": ((1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)),
+    "FCC": ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)),
+}
+LATTICES = {"CC": L_CC, "BCC": L_BCC, "FCC": L_FCC}
+
+
 @dataclass(frozen=True)
 class Config:
     name: str
@@ -67,10 +78,19 @@ class Config:
     passes: str = "fwd"    # 'fwd', 'fwd+grad', 'mse'
     lookups: int = 0       # sites with nonzero weight per query (Table 1 column)
     extra: dict = field(default_factory=dict)
+    voronoi: tuple = None  # (lattice of the Voronoi cell, n) for phi = |det L| V_n; Xi is None then
 
     @property
     def s(self):
-        return self.Xi.shape[0]
+        return self.L.shape[0]
+
+    @property
+    def Lv(self):
+        return LATTICES[self.voronoi[0]] if self.voronoi else None
+
+    @property
+    def voronoi_gen(self):
+        return VORONOI_GEN[self.voronoi[0]] if self.voronoi else None
 
     @property
     def M(self):
@@ -114,6 +134,19 @@ CONFIGS = {
     "bcc_quintic_rd": Config("bcc_quintic_rd", "BCC 2x32^3, the BCC diagonals twice (Table 1 quintic rhombic "
                              "dodecahedron)", L_BCC, np.hstack([BCC_DIAG] * 2), 2, (_z(3), (1, 1, 1)), (32, 32, 32),
                              1 << 20, 5.0, 58.0, "uniform", lookups=32),
+    # Voronoi splines (Sec. 3; Table 1 Voronoi rows): phi = |det L| V_n of the BCC / FCC Voronoi cell
+    "vor_bcc1": Config("vor_bcc1", "BCC 2x32^3, BCC Voronoi spline 1", L_BCC, None, 2, (_z(3), (1, 1, 1)),
+                       (32, 32, 32), 1 << 20, 3.0, 60.0, "uniform", lookups=8, voronoi=("BCC", 1)),
+    "vor_fcc1": Config("vor_fcc1", "FCC 4x32^3, FCC Voronoi spline 1", L_FCC, None, 2,
+                       (_z(3), (1, 1, 0), (1, 0, 1), (0, 1, 1)), (32, 32, 32), 1 << 20, 3.0, 60.0, "uniform",
+                       lookups=8, voronoi=("FCC", 1)),
+    "vor_cc_bcc1": Config("vor_cc_bcc1", "Z^3 64^3, BCC Voronoi spline 1 on the Cartesian lattice", L_CC, None, 1,
+                          (_z(3),), (64, 64, 64), 1 << 20, 2.0, 61.0, "uniform", lookups=32, voronoi=("BCC", 1)),
+    "vor_cc_fcc1": Config("vor_cc_fcc1", "Z^3 64^3, FCC Voronoi spline 1 on the Cartesian lattice", L_CC, None, 1,
+                          (_z(3),), (64, 64, 64), 1 << 20, 2.0, 61.0, "uniform", lookups=16, voronoi=("FCC", 1)),
+    "vor_fcc2": Config("vor_fcc2", "FCC 4x32^3, FCC Voronoi spline 2", L_FCC, None, 2,
+                       (_z(3), (1, 1, 0), (1, 0, 1), (0, 1, 1)), (32, 32, 32), 1 << 20, 4.0, 59.0, "uniform",
+                       lookups=27, voronoi=("FCC", 2)),
 }
 
 
