@@ -36,7 +36,8 @@ import numpy as np
 
 from .lattice import Lattice, primitive_normal
 from .poly import Poly, monomials
-from .pp import BoxSplinePP, DegeneratePoint
+from .phi import BoxPhi
+from .pp import DegeneratePoint
 
 
 # ------------------------------------------------------------------ symmetry
@@ -96,70 +97,62 @@ def chamber_vertices(s, fold, h):
     return vs
 
 
+def plane_ties(t):
+    """Per splitting plane of tables t: True when a point exactly on the plane
+    takes its >= side (the side of the chamber's generic tie point)."""
+    from .select import tie_sides
+    h = Fraction(t.D, 2)
+    return tie_sides(t.planes, chamber_constraints(t.s, t.fold, h), chamber_vertices(t.s, t.fold, h))
+
+
 # ------------------------------------------------------------------ analysis
 class SplineTables:
-    def __init__(self, name, L, Xi, seed=1):
+    def __init__(self, name, L, Xi=None, seed=1, phi=None):
+        """Tables for phi on the lattice L: the box spline M_Xi when `phi` is
+        None, else the given basis function object (see `phi.py`)."""
         self.name = name
         self.lat = Lattice(L)
-        Xi = [[int(v) for v in row] for row in Xi]
-        self.Xi_rows = Xi
-        self.s = s = len(Xi)
-        self.n = n = len(Xi[0])
-        self.cols = [tuple(Xi[a][j] for a in range(s)) for j in range(n)]
-        for c in self.cols:
-            if not self.lat.contains(c):
-                raise ValueError("direction not on the lattice: partition of unity fails")
+        s = self.lat.s
+        if phi is None:
+            phi = BoxPhi(Xi, self.lat.det)
+            for c in phi.cols:
+                if not self.lat.contains(c):
+                    raise ValueError("direction not on the lattice: partition of unity fails")
+        self.phi = phi
+        self.s = s
+        self.voronoi = None
+        if phi.kind == "voronoi":
+            self.voronoi = {"Lv": phi.vlat.L, "W": [list(w) for w in phi.W], "sigma": phi.sigma, "n": phi.n,
+                            "terms": phi.n_box}
+        dirs = phi.mesh_directions()
+        self.Xi_rows = [[d[a] for d in dirs] for a in range(s)]
+        self.n = len(dirs)
+        self.cols = [tuple(d) for d in dirs]
         self.D = self.lat.D
         self.h = Fraction(self.D, 2)
-        self.c0 = tuple(Fraction(sum(c[a] for c in self.cols), 2) for a in range(s))
-        self.degree = n - s
-        self.order = self._order()
-        self.fold = symmetry_fold(self.cols, s)
-        self.pp = BoxSplinePP(Xi)
+        self.degree = phi.degree
+        self.order = phi.order
+        self.fold = symmetry_fold(phi.symmetry_generators(), s)
         self._rng = np.random.default_rng(seed)
-        self.normals = self._normals()
+        self.normals = phi.normals()
         self.planes = self._splitting_planes()
         self.cells = self._cells()
         self.K = len(self.cells)
         self.orbit_table = self._orbit_table()
+        self.sigma = self._sigma()
         self.orbits = [self._orbit(c) for c in self.cells]
-
-    # ---------------------------------------------------------------- basics
-    def _order(self):
-        from .lattice import int_rank
-        for r in range(1, self.n + 1):
-            for rem in combinations(range(self.n), r):
-                keep = [c for j, c in enumerate(self.cols) if j not in rem]
-                if int_rank([[c[a] for c in keep] for a in range(self.s)] if keep else [[0]]) < self.s:
-                    return r
-        return self.n
-
-    def _normals(self):
-        out = set()
-        for sub in combinations(self.cols, self.s - 1):
-            nu = primitive_normal(list(sub), self.s)
-            if nu is not None:
-                out.add(nu)
-        return sorted(out)
 
     def _splitting_planes(self):
         """Mesh planes nu.u' = off crossing the interior of F.  Site j's copy of
         phi has breakpoints at nu.(u - D(j - 1/2) + c0) = nu.(sum of a subset)."""
         s, D = self.s, self.D
         verts = chamber_vertices(s, self.fold, self.h)
-        sums = set()
-        for r in range(self.n + 1):
-            for sub in combinations(self.cols, r):
-                sums.add(tuple(sum(c[a] for c in sub) for a in range(s)))
         planes = []
         for nu in self.normals:
             vals = [sum(Fraction(a) * b for a, b in zip(nu, v)) for v in verts]
             lo, hi = min(vals), max(vals)
-            base = set()
-            for sm in sums:
-                # nu.u = nu.(sum - c0) + D nu.(j - 1/2 1), j integer
-                off = sum(Fraction(a) * (b - c) for a, b, c in zip(nu, sm, self.c0)) - self.h * sum(nu)
-                base.add(off)
+            # nu.u = b + D nu.(j - 1/2 1), j integer, b a breakpoint offset of phi
+            base = {b - self.h * sum(nu) for b in self.phi.offsets(nu)}
             offs = set()
             for off in base:
                 # nu is primitive, so nu.(D Z^s) = D Z
@@ -257,23 +250,36 @@ class SplineTables:
                 table.append(sig[best])
         return table
 
+    def feasible_codes(self):
+        return {sum(1 << i for i, b in enumerate(c[0]) if b == 1): k for k, c in enumerate(self.cells)}
+
+    def _sigma(self):
+        """Sec. 4.2 table sigma(q mod r) when the full 2^Q table no longer fits
+        one 64-bit word of 4-bit entries (Q > 4); None otherwise."""
+        from .select import sigma_table
+        Q = len(self.planes)
+        if 4 * (1 << Q) <= 64:
+            return None
+        r, table = sigma_table(self.feasible_codes(), Q)
+        return {"r": r, "table": table, "feasible": sorted(self.feasible_codes())}
+
     def _orbit(self, cell):
         signs, u0 = cell
         s, D = self.s, self.D
-        R = [int((Fraction(sum(abs(c[a]) for c in self.cols), 2) + self.h) / D) + 2 for a in range(s)]
+        R = [int((self.phi.reach[a] + self.h) / D) + 2 for a in range(s)]
         cand = list(product(*[range(-R[a], R[a] + 2) for a in range(s)]))
         for attempt in range(20):
             try:
                 u = self._generic(u0, signs)
                 stencil, polys = [], []
                 for j in cand:
-                    shift = tuple(self.c0[a] - D * (Fraction(j[a]) - Fraction(1, 2)) for a in range(s))
-                    q = tuple(u[a] + shift[a] for a in range(s))
-                    P = self.pp.piece(q)
+                    # site j of the cell sits at D (j - 1/2 1) from the cell centre
+                    shift = tuple(-D * (Fraction(j[a]) - Fraction(1, 2)) for a in range(s))
+                    P = self.phi.piece(tuple(u[a] + shift[a] for a in range(s)))
                     if P.is_zero():
                         continue
                     stencil.append(tuple(j))
-                    polys.append(P.shift(shift).scale(self.lat.det))
+                    polys.append(P.shift(shift))
                 return {"stencil": stencil, "polys": polys, "point": u}
             except DegeneratePoint:
                 continue

@@ -9,9 +9,8 @@ import os
 import sys
 import time
 
-from .analysis import SplineTables
 from .emit import write
-from .specs import SPECS
+from .specs import SPECS, make_tables
 
 OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "csrc", "generated")
 
@@ -35,9 +34,9 @@ def main(names):
     if names and names[0] == "--reemit":
         return reemit(names[1:])
     for name in names or list(SPECS):
-        struct, L, Xi = SPECS[name]
+        struct = SPECS[name][0]
         t0 = time.time()
-        t = SplineTables(name, L, Xi)
+        t = make_tables(name)
         t.verify()
         write(t, OUT, struct)
         print(f"{name}: K={t.K} Q={len(t.planes)} stencils={t.lookups_per_coset()} ({time.time() - t0:.1f} s)",

@@ -41,10 +41,16 @@ def site_offset(j, perm, tau):
 
 
 def orbit_of(tables, up):
+    from .analysis import plane_ties
+    ties = plane_ties(tables)
     code = 0
     for i, (nu, off) in enumerate(tables.planes):
-        if sum(a * b for a, b in zip(nu, up)) - off >= 0:
+        v = sum(a * b for a, b in zip(nu, up)) - off
+        if v > 0 or (v == 0 and ties[i]):
             code |= 1 << i
+    sig = getattr(tables, "sigma", None)
+    if sig:
+        return sig["table"][code % sig["r"]]          # Sec. 4.2: sigma(q mod r)
     return tables.orbit_table[code]
 
 
@@ -78,7 +84,11 @@ class FloatTables:
                   for k in range(tables.K)]
         self.stencil = [np.array(o["stencil"], dtype=np.int64) for o in tables.orbits]
         self.planes = [(np.array(nu, dtype=float), float(off)) for nu, off in tables.planes]
+        from .analysis import plane_ties
+        self.ties = plane_ties(tables)
         self.orbit_table = np.array(tables.orbit_table, dtype=np.int64)
+        sig = getattr(tables, "sigma", None)
+        self.sigma = (sig["r"], np.array(sig["table"], dtype=np.int64)) if sig else None
 
 
 def eval_fp64(ft, coeffs, X):
@@ -101,9 +111,10 @@ def eval_fp64(ft, coeffs, X):
             tau[odd, -1] *= -1
         up = tau * np.take_along_axis(u, perm, axis=1)
         code = np.zeros(len(X), dtype=np.int64)
-        for b, (nu, off) in enumerate(ft.planes):
-            code |= ((up @ nu - off) >= 0).astype(np.int64) << b
-        orbit = ft.orbit_table[code]
+        for b, ((nu, off), tie) in enumerate(zip(ft.planes, ft.ties)):
+            v = up @ nu - off
+            code |= ((v > 0) | ((v == 0) & tie)).astype(np.int64) << b
+        orbit = ft.orbit_table[code] if ft.sigma is None else ft.sigma[1][code % ft.sigma[0]]
         mono = np.stack([np.prod(up ** np.array(e), axis=1) for e in ft.mons], axis=1)
         flat_c = coeffs[k].reshape(-1)
         for ob in range(t.K):

@@ -58,6 +58,11 @@ class Poly:
             return Poly(self.nv)
         return Poly(self.nv, {e: c * k for e, c in self.t.items()})
 
+    def scale_vars(self, k):
+        """Q(z) = P(k z) for a scalar k."""
+        k = Fraction(k)
+        return Poly(self.nv, {e: c * k ** sum(e) for e, c in self.t.items()})
+
     def __mul__(self, o):
         r = {}
         for e1, c1 in self.t.items():

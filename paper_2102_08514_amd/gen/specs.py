@@ -1,4 +1,14 @@
-"""The splines the library ships tables for (lattice matrix, direction matrix)."""
+"""The splines the library ships tables for.
+
+Box splines: (struct name, lattice matrix L, direction matrix Xi).
+Voronoi splines (Sec. 3): (struct name, L, VoronoiSpec(L_v, generators W,
+sigma, n)) for phi = |det L| V_n of the Voronoi cell of L_v, a zonotope
+sum_j [-1/2, 1/2] W_j / sigma (checked when the tables are built).
+"""
+
+from collections import namedtuple
+
+VoronoiSpec = namedtuple("VoronoiSpec", "Lv W sigma n")
 
 I3 = [[1, 0, 0], [0, 1, 0], [0, 0, 1]]
 BCC_DIAG = [[-1, 1, 1, -1], [1, -1, 1, -1], [1, 1, -1, -1]]
@@ -24,6 +34,10 @@ XI_D4 = [[1, 1, 1, 1, -1, -1, -1, -1], [1, 1, -1, -1, 1, 1, -1, -1], [1, -1, 1, 
 I4 = [[int(a == b) for b in range(4)] for a in range(4)]
 HAD4_COLS = [list(r) for r in zip(*HAD4)]  # columns of the Hadamard matrix as rows
 
+# Voronoi cells: the truncated octahedron of BCC and the rhombic dodecahedron of FCC
+W_BCC_CELL = [(1, 1, 0), (1, -1, 0), (1, 0, 1), (1, 0, -1), (0, 1, 1), (0, 1, -1)]
+W_FCC_CELL = [(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)]
+
 SPECS = {
     # name: (struct name, L, Xi)
     "bcc_linear": ("SplineBccLinear", L_BCC, BCC_DIAG),
@@ -38,4 +52,20 @@ SPECS = {
     "cc_tp4": ("SplineCcTp4", L_CC, _hcat(I3, I3, I3, I3)),
     "cc_linear_rd": ("SplineCcLinearRd", L_CC, BCC_DIAG),
     "bcc_quintic_rd": ("SplineBccQuinticRd", L_BCC, _hcat(BCC_DIAG, BCC_DIAG)),
+    # Voronoi splines (Table 1 Voronoi rows)
+    "bcc_voronoi1": ("SplineBccVoronoi1", L_BCC, VoronoiSpec(L_BCC, W_BCC_CELL, 2, 1)),
+    "fcc_voronoi1": ("SplineFccVoronoi1", L_FCC, VoronoiSpec(L_FCC, W_FCC_CELL, 2, 1)),
+    "cc_bcc_voronoi1": ("SplineCcBccVoronoi1", L_CC, VoronoiSpec(L_BCC, W_BCC_CELL, 2, 1)),
+    "cc_fcc_voronoi1": ("SplineCcFccVoronoi1", L_CC, VoronoiSpec(L_FCC, W_FCC_CELL, 2, 1)),
+    "fcc_voronoi2": ("SplineFccVoronoi2", L_FCC, VoronoiSpec(L_FCC, W_FCC_CELL, 2, 2)),
 }
+
+
+def make_tables(name):
+    """Run the analysis for a shipped spline."""
+    from .analysis import SplineTables
+    from .phi import VoronoiPhi
+    _, L, what = SPECS[name]
+    if isinstance(what, VoronoiSpec):
+        return SplineTables(name, L, phi=VoronoiPhi(L, what.Lv, what.W, what.sigma, what.n))
+    return SplineTables(name, L, what)

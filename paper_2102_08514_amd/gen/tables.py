@@ -38,6 +38,8 @@ class LoadedTables:
         self.order = r["order"]
         self.planes = [(tuple(nu), Fraction(off)) for nu, off in r["planes"]]
         self.orbit_table = list(r["orbit_table"])
+        self.sigma = r.get("sigma")
+        self.voronoi = r.get("voronoi")
         self._mons = [tuple(e) for e in r["monomials"]]
         self._A = [[[Fraction(v) for v in row] for row in o["A"]] for o in r["orbits"]]
         self.orbits = []
