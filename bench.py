@@ -155,20 +155,27 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
 
 
 # ------------------------------------------------------------------ committed counter summaries
-_SRC_DIRS = ("paper_2102_08514_amd/csrc", "paper_2102_08514_amd/csrc/generated")
+_CSRC = "paper_2102_08514_amd/csrc"
+_SHARED_SRC = ("lsp_kernels.hip", "lsp_binned.hip", "lsp_launch.hip", "lsp_internal.h", "lsp_api.hip")
+SPLINE_OF = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir",
+             "d4": "d4_8dir"}
 
 
-def kernel_source_digest():
-    """sha256 over the HIP sources and generated tables the library is built from."""
+def kernel_source_digest(config=None):
+    """sha256 over the shared HIP sources and the generated table of the
+    workload's spline (every table when config is None)."""
     import hashlib
     h = hashlib.sha256()
-    for d in _SRC_DIRS:
-        full = os.path.join(ROOT, d)
-        for name in sorted(os.listdir(full)):
-            if name.endswith((".hip", ".h", ".inc")):
-                h.update(name.encode())
-                with open(os.path.join(full, name), "rb") as fh:
-                    h.update(fh.read())
+    names = list(_SHARED_SRC)
+    gen = os.path.join(ROOT, _CSRC, "generated")
+    if config is None:
+        names += [os.path.join("generated", n) for n in sorted(os.listdir(gen)) if n.endswith(".inc")]
+    else:
+        names.append(os.path.join("generated", SPLINE_OF[config] + ".inc"))
+    for name in names:
+        h.update(os.path.basename(name).encode())
+        with open(os.path.join(ROOT, _CSRC, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -181,7 +188,7 @@ def profile_counters(config, dtype):
     out, srcs = {}, set()
     if not os.path.isdir(pdir):
         return out
-    digest = kernel_source_digest()
+    digest = kernel_source_digest(config)
     for name in sorted(os.listdir(pdir)):
         if not name.endswith(".md"):
             continue
@@ -230,17 +237,20 @@ def roofline(kernel, n, seconds, bytes_per, flops_per, counters):
            "effective_hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_sample": round(bytes_per, 3)}}
     c = counters.get(kernel)
-    if c:
-        fetch, write = c.get("fetch_bytes"), c.get("write_bytes")
-        if fetch is not None and write is not None:
-            rec["traffic"] = fetch + write
-            rec["hbm_frac_measured"] = round((fetch + write) / seconds / 1e9 / HBM_PEAK_GBS, 4)
+    if c and "read_bytes" in c and "write_bytes" in c:
+        # bytes between L2 and the memory fabric per launch (size-class request
+        # counters; Infinity-Cache hits included, so an upper bound on HBM bytes)
+        traffic = c["read_bytes"] + c["write_bytes"]
+        rec["traffic"] = int(traffic)
+        rec["dram"] = {"achieved": round(traffic / seconds / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(traffic / seconds / 1e9 / HBM_PEAK_GBS, 4),
+                       "read_bytes": int(c["read_bytes"]), "write_bytes": int(c["write_bytes"])}
         if "valu_insts" in c:
-            # wave-level VALU instructions x 64 lanes against 64 lanes per CU per clock
-            rec["valu_issue_frac"] = round(c["valu_insts"] * 64 / seconds / (256 * 64 * 2.4e9), 4)
-        for key in ("valu_busy_pct", "l2_hit_pct", "lds_bank_conflict_pct", "mall_read_bytes", "mall_write_bytes"):
+            # wave-level VALU instructions, 4 cycles each on a 16-lane SIMD, 4 SIMDs per CU
+            rec["valu_issue_frac"] = round(c["valu_insts"] / (256 * 2.4e9 * seconds), 4)
+        for key in ("valu_busy_pct", "l2_hit_pct", "lds_bank_conflict_pct", "dur_us"):
             if key in c:
-                rec[key] = c[key]
+                rec["profiled_" + key if key == "dur_us" else key] = round(c[key], 2)
         rec["counter_source"] = counters.get("_source")
     return rec
 
@@ -487,7 +497,7 @@ def run_workload(name, dtype, args, torch, lsp, W, I, headline=False):
         rec["cpu_baseline"] = cb
         rec["accuracy"] = error_record(f[:len(idx)].double().cpu().numpy(), want, w.coeffs,
                                        f"stored coefficients, first {len(idx)} queries")
-    rec["kernel_source_digest"] = kernel_source_digest()
+    rec["kernel_source_digest"] = kernel_source_digest(name)
     rec["wall_s"] = round(time.perf_counter() - t0, 1)
     w.release()
     return rec

@@ -34,7 +34,11 @@
  *    the default stream).
  *  - Supported splines: the library ships generated tables for a fixed set
  *    of (lattice, direction matrix) pairs (lsp_plan_create matches L by its
- *    coset structure and Xi up to column order and column signs).
+ *    coset structure and Xi up to column order and column signs), and of
+ *    Voronoi splines (lsp_plan_create_voronoi): phi = |det L| V_n, with V_n
+ *    the (n+1)-fold self-convolution of the normalised indicator of the
+ *    Voronoi cell of a lattice L_v contained in L (Sec. 3, Voronoi splines).
+ *    Every entry point below works the same for both kinds of plan.
  */
 #ifndef LSP_H
 #define LSP_H
@@ -91,6 +95,8 @@ typedef struct {
   int32_t fma_b[16];
   int32_t fma_w[16];
   int32_t grad_terms;
+  int32_t kind;             /* 0: box spline; 1: Voronoi spline (n_dirs counts the cell's zonotope generators) */
+  int32_t voronoi_n;        /* Voronoi splines: n of V_n */
 } lsp_info;
 
 /* Create a plan for lattice L (s x s, row-major; columns generate the lattice)
@@ -100,6 +106,18 @@ typedef struct {
  * partition of unity), LSP_ERR_UNSUPPORTED.  flags: reserved, pass 0. */
 lsp_status lsp_plan_create(int32_t s, const int32_t* L, int32_t n, const int32_t* Xi, uint32_t flags,
                            lsp_plan* out);
+/* Create a plan for the Voronoi spline V_n of the lattice Lv (s x s,
+ * row-major, columns generate it) used on the lattice L (s x s): phi(w) =
+ * |det L| V_n(w), V_0 = 1/|det Lv| on the Voronoi cell of Lv (the points at
+ * least as close to the origin as to any other site of Lv) and V_n =
+ * V_0 * V_{n-1} (Sec. 3, Voronoi splines).  phi is a partition of unity on L
+ * because Lv is a sublattice of L.  Shipped: BCC and FCC V_1 on their own
+ * lattices and on Z^3, FCC V_2 on FCC (Table 1's Voronoi rows).  Lv is
+ * matched as a lattice (any basis).  Errors: LSP_ERR_NULL, LSP_ERR_INVALID
+ * (singular L or Lv, n < 1), LSP_ERR_NOT_ON_LATTICE (Lv not inside L),
+ * LSP_ERR_UNSUPPORTED (no tables).  flags: reserved, pass 0. */
+lsp_status lsp_plan_create_voronoi(int32_t s, const int32_t* L, const int32_t* Lv, int32_t n, uint32_t flags,
+                                   lsp_plan* out);
 lsp_status lsp_plan_info(lsp_plan plan, lsp_info* out);
 lsp_status lsp_plan_destroy(lsp_plan plan);
 

@@ -14,7 +14,7 @@ LSP_F32, LSP_BF16, LSP_F16, LSP_F64 = 0, 1, 2, 3
 
 # every symbol declared in include/lsp.h
 EXPORTS = (
-    "lsp_plan_create", "lsp_plan_info", "lsp_plan_destroy", "lsp_vol_bind", "lsp_vol_release",
+    "lsp_plan_create", "lsp_plan_create_voronoi", "lsp_plan_info", "lsp_plan_destroy", "lsp_vol_bind", "lsp_vol_release",
     "lsp_eval", "lsp_eval_mse", "lsp_eval_adjoint", "lsp_eval_rays", "lsp_status_string",
     "lsp_schedule_size", "lsp_schedule", "lsp_eval_scheduled", "lsp_eval_mse_scheduled",
     "lsp_eval_adjoint_scheduled", "lsp_render", "lsp_mse_backward_scheduled",
@@ -29,7 +29,7 @@ class LspInfo(ctypes.Structure):
         ("stencil", ctypes.c_int32 * 16), ("lookups", ctypes.c_int32), ("n_monomials", ctypes.c_int32),
         ("nnz", ctypes.c_int32 * 16), ("offset_min", ctypes.c_int32), ("offset_max", ctypes.c_int32),
         ("name", ctypes.c_char * 32), ("fma_b", ctypes.c_int32 * 16), ("fma_w", ctypes.c_int32 * 16),
-        ("grad_terms", ctypes.c_int32),
+        ("grad_terms", ctypes.c_int32), ("kind", ctypes.c_int32), ("voronoi_n", ctypes.c_int32),
     ]
 
 
@@ -58,6 +58,7 @@ def lib():
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         P = ctypes.POINTER
         L.lsp_plan_create.argtypes = [i32, P(i32), i32, P(i32), u32, P(vp)]
+        L.lsp_plan_create_voronoi.argtypes = [i32, P(i32), P(i32), i32, u32, P(vp)]
         L.lsp_plan_info.argtypes = [vp, P(LspInfo)]
         L.lsp_plan_destroy.argtypes = [vp]
         L.lsp_vol_bind.argtypes = [vp, i32, P(vp), P(i64), P(vp)]
@@ -110,6 +111,16 @@ def lsp_plan_create(L, Xi, flags=0):
     return out
 
 
+def lsp_plan_create_voronoi(L, Lv, n, flags=0):
+    """L, Lv: s x s integer matrices; n: the Voronoi spline's index (V_n)."""
+    L = [[int(v) for v in row] for row in L]
+    Lv = [[int(v) for v in row] for row in Lv]
+    out = ctypes.c_void_p()
+    check(lib().lsp_plan_create_voronoi(len(L), _i32_array(sum(L, [])), _i32_array(sum(Lv, [])), int(n), flags,
+                                        ctypes.byref(out)), "lsp_plan_create_voronoi")
+    return out
+
+
 def lsp_plan_info(plan):
     info = LspInfo()
     check(lib().lsp_plan_info(plan, ctypes.byref(info)), "lsp_plan_info")
@@ -122,7 +133,8 @@ def lsp_plan_info(plan):
         "n_monomials": info.n_monomials, "nnz": [info.nnz[k] for k in range(K)],
         "offset_min": info.offset_min, "offset_max": info.offset_max,
         "fma_b": [info.fma_b[k] for k in range(K)], "fma_w": [info.fma_w[k] for k in range(K)],
-        "grad_terms": info.grad_terms,
+        "grad_terms": info.grad_terms, "kind": "voronoi" if info.kind == 1 else "box",
+        "voronoi_n": info.voronoi_n,
     }
 
 

@@ -100,10 +100,17 @@ class Schedule:
 
 
 class LatticeSpline:
-    """A plan for lattice L and direction matrix Xi (generated tables must exist)."""
+    """A plan for lattice L and direction matrix Xi, or, with voronoi=(Lv, n),
+    for the Voronoi spline V_n of the lattice Lv on L (generated tables must
+    exist)."""
 
-    def __init__(self, L_matrix, Xi):
-        self.plan = L.lsp_plan_create(L_matrix, Xi)
+    def __init__(self, L_matrix, Xi=None, voronoi=None):
+        if (Xi is None) == (voronoi is None):
+            raise ValueError("give either a direction matrix Xi or voronoi=(Lv, n)")
+        if voronoi is not None:
+            self.plan = L.lsp_plan_create_voronoi(L_matrix, voronoi[0], voronoi[1])
+        else:
+            self.plan = L.lsp_plan_create(L_matrix, Xi)
         self.info = L.lsp_plan_info(self.plan)
         self.s = self.info["s"]
 

@@ -21,7 +21,8 @@ using namespace lsp;
 
 enum SpecId {
   kBccLinear = 0, kCcZp, kBccQuartic, kFcc6, kD4s8, kD48,
-  kCcTp2, kCcTp3, kCcTp4, kCcLinearRd, kBccQuinticRd, kNumSpecs
+  kCcTp2, kCcTp3, kCcTp4, kCcLinearRd, kBccQuinticRd,
+  kBccVoronoi1, kFccVoronoi1, kCcBccVoronoi1, kCcFccVoronoi1, kFccVoronoi2, kNumSpecs
 };
 
 struct SpecDesc {
@@ -32,6 +33,9 @@ struct SpecDesc {
   std::vector<int> nsite, nnz, fma_b, fma_w;
   int lookups;
   int grad_terms;
+  int kind;                                // 0 box spline, 1 Voronoi spline
+  int vor_n;                               // Voronoi: V_n
+  std::vector<std::vector<long long>> vor_lv;  // Voronoi: the cell's lattice (s x s, row-major rows)
 };
 
 template <class SP>
@@ -49,6 +53,12 @@ SpecDesc describe(const char* name) {
     d.fma_b.push_back(SP::FMA_B[k]);
     d.fma_w.push_back(SP::FMA_W[k]);
   }
+  d.kind = SP::KIND;
+  d.vor_n = 0;
+  if constexpr (SP::KIND == 1) {
+    d.vor_n = SP::VOR_N;
+    for (int r = 0; r < SP::S; ++r) d.vor_lv.emplace_back(SP::VOR_LV[r], SP::VOR_LV[r] + SP::S);
+  }
   d.grad_terms = 0;
   for (int m = 0; m < SP::NMON; ++m)
     for (int r = 0; r < SP::S; ++r) d.grad_terms += SP::MDER[m][r] >= 0 ? 1 : 0;
@@ -61,7 +71,10 @@ const std::vector<SpecDesc>& specs() {
       describe<SplineBccQuartic>("bcc_quartic"), describe<SplineFcc6>("fcc_6dir"),
       describe<SplineD4s8>("d4s_8dir"), describe<SplineD48>("d4_8dir"),
       describe<SplineCcTp2>("cc_tp2"), describe<SplineCcTp3>("cc_tp3"), describe<SplineCcTp4>("cc_tp4"),
-      describe<SplineCcLinearRd>("cc_linear_rd"), describe<SplineBccQuinticRd>("bcc_quintic_rd")};
+      describe<SplineCcLinearRd>("cc_linear_rd"), describe<SplineBccQuinticRd>("bcc_quintic_rd"),
+      describe<SplineBccVoronoi1>("bcc_voronoi1"), describe<SplineFccVoronoi1>("fcc_voronoi1"),
+      describe<SplineCcBccVoronoi1>("cc_bcc_voronoi1"), describe<SplineCcFccVoronoi1>("cc_fcc_voronoi1"),
+      describe<SplineFccVoronoi2>("fcc_voronoi2")};
   return all;
 }
 
@@ -128,6 +141,48 @@ std::vector<int> canon_dir(std::vector<int> v) {
   std::vector<int> neg(v.size());
   for (size_t i = 0; i < v.size(); ++i) neg[i] = -v[i];
   return std::max(v, neg);
+}
+
+// |det L|, the adjugate, D (smallest positive integer with D L^{-1} integral)
+// and the coset shifts of L Z^s in [0, D)^s, ordered by sum_a l_a D^a.
+struct LatticeShape {
+  long long det;
+  long long D;
+  std::vector<std::vector<long long>> adj;
+  std::vector<std::vector<int>> shifts;
+};
+
+bool lattice_shape(int s, const int32_t* L, LatticeShape& out) {
+  std::vector<std::vector<long long>> A(s, std::vector<long long>(s));
+  for (int r = 0; r < s; ++r)
+    for (int c = 0; c < s; ++c) A[r][c] = L[r * s + c];
+  const long long det = det_int(A);
+  if (det == 0) return false;
+  out.adj = adj_int(A);  // L^{-1} = adj / det
+  out.det = det < 0 ? -det : det;
+  long long g = det;
+  for (auto& row : out.adj)
+    for (long long v : row) g = gcdll(g, v);
+  out.D = out.det / g;
+  out.shifts.clear();
+  std::vector<long long> v(s, 0);
+  long long total = 1;
+  for (int a = 0; a < s; ++a) total *= out.D;
+  for (long long code = 0; code < total; ++code) {
+    long long c = code;
+    std::vector<int> vi(s);
+    for (int a = 0; a < s; ++a) { v[a] = c % out.D; vi[a] = static_cast<int>(v[a]); c /= out.D; }
+    if (on_lattice(out.adj, det, v)) out.shifts.push_back(vi);
+  }
+  return true;
+}
+
+lsp_status make_plan(int id, lsp_plan* out) {
+  lsp_plan p = new (std::nothrow) lsp_plan_s;
+  if (!p) return LSP_ERR_INVALID;
+  p->spec = id;
+  *out = p;
+  return LSP_OK;
 }
 
 // Launch limits of the given-order kernels: one work item per lane in a 1-D
@@ -201,6 +256,11 @@ bool sched_matches(const void* ws, const SchedKey& k) {
     case kCcTp4: return lsp_host::FN<SplineCcTp4>(__VA_ARGS__);         \
     case kCcLinearRd: return lsp_host::FN<SplineCcLinearRd>(__VA_ARGS__); \
     case kBccQuinticRd: return lsp_host::FN<SplineBccQuinticRd>(__VA_ARGS__); \
+    case kBccVoronoi1: return lsp_host::FN<SplineBccVoronoi1>(__VA_ARGS__); \
+    case kFccVoronoi1: return lsp_host::FN<SplineFccVoronoi1>(__VA_ARGS__); \
+    case kCcBccVoronoi1: return lsp_host::FN<SplineCcBccVoronoi1>(__VA_ARGS__); \
+    case kCcFccVoronoi1: return lsp_host::FN<SplineCcFccVoronoi1>(__VA_ARGS__); \
+    case kFccVoronoi2: return lsp_host::FN<SplineFccVoronoi2>(__VA_ARGS__); \
   }                                                                   \
   return LSP_ERR_UNSUPPORTED;
 
@@ -228,29 +288,19 @@ lsp_status lsp_plan_create(int32_t s, const int32_t* L, int32_t n, const int32_t
   if (!L || !Xi || !out) return LSP_ERR_NULL;
   *out = nullptr;
   if (s < 1 || s > 4 || n < s || n > 16) return LSP_ERR_INVALID;
-  std::vector<std::vector<long long>> A(s, std::vector<long long>(s));
-  for (int r = 0; r < s; ++r)
-    for (int c = 0; c < s; ++c) A[r][c] = L[r * s + c];
-  const long long det = det_int(A);
-  if (det == 0) return LSP_ERR_INVALID;
-  const auto adj = adj_int(A);  // L^{-1} = adj / det
-  // D: smallest positive integer with D L^{-1} integral
-  long long g = det;
-  for (auto& row : adj)
-    for (long long v : row) g = gcdll(g, v);
-  const long long D = (det < 0 ? -det : det) / g;
+  LatticeShape lat;
+  if (!lattice_shape(s, L, lat)) return LSP_ERR_INVALID;
   std::vector<std::vector<int>> dirs;
   for (int j = 0; j < n; ++j) {
     std::vector<long long> v(s);
     std::vector<int> vi(s);
     for (int a = 0; a < s; ++a) { v[a] = Xi[a * n + j]; vi[a] = Xi[a * n + j]; }
-    if (!on_lattice(adj, det, v)) return LSP_ERR_NOT_ON_LATTICE;
+    if (!on_lattice(lat.adj, lat.det, v)) return LSP_ERR_NOT_ON_LATTICE;
     dirs.push_back(canon_dir(vi));
   }
   // rank of Xi must be s
   {
     bool spans = false;
-    std::vector<int> idx(s);
     // try all s-subsets of columns for a nonzero determinant
     std::vector<int> sel(n, 0);
     std::fill(sel.begin(), sel.begin() + s, 1);
@@ -268,32 +318,52 @@ lsp_status lsp_plan_create(int32_t s, const int32_t* L, int32_t n, const int32_t
     if (!spans) return LSP_ERR_INVALID;
   }
   std::sort(dirs.begin(), dirs.end());
-  // coset shifts of L Z^s in [0, D)^s
-  std::vector<std::vector<int>> shifts;
-  {
-    std::vector<long long> v(s, 0);
-    long long total = 1;
-    for (int a = 0; a < s; ++a) total *= D;
-    for (long long code = 0; code < total; ++code) {
-      long long c = code;
-      std::vector<int> vi(s);
-      for (int a = 0; a < s; ++a) { v[a] = c % D; vi[a] = static_cast<int>(v[a]); c /= D; }
-      if (on_lattice(adj, det, v)) shifts.push_back(vi);
-    }
-  }
   for (int id = 0; id < kNumSpecs; ++id) {
     const SpecDesc& sd = specs()[id];
-    if (sd.s != s || sd.ndir != n || sd.D != D || sd.M != static_cast<int>(shifts.size())) continue;
+    if (sd.kind != 0 || sd.s != s || sd.ndir != n || sd.D != lat.D ||
+        sd.M != static_cast<int>(lat.shifts.size()))
+      continue;
     std::vector<std::vector<int>> sdirs;
     for (auto& dv : sd.dirs) sdirs.push_back(canon_dir(dv));
     std::sort(sdirs.begin(), sdirs.end());
     if (sdirs != dirs) continue;
-    if (sd.shifts != shifts) continue;
-    lsp_plan p = new (std::nothrow) lsp_plan_s;
-    if (!p) return LSP_ERR_INVALID;
-    p->spec = id;
-    *out = p;
-    return LSP_OK;
+    if (sd.shifts != lat.shifts) continue;
+    return make_plan(id, out);
+  }
+  return LSP_ERR_UNSUPPORTED;
+}
+
+lsp_status lsp_plan_create_voronoi(int32_t s, const int32_t* L, const int32_t* Lv, int32_t n, uint32_t flags,
+                                   lsp_plan* out) {
+  (void)flags;
+  if (!L || !Lv || !out) return LSP_ERR_NULL;
+  *out = nullptr;
+  if (s < 1 || s > 4 || n < 1) return LSP_ERR_INVALID;
+  LatticeShape lat, vlat;
+  if (!lattice_shape(s, L, lat) || !lattice_shape(s, Lv, vlat)) return LSP_ERR_INVALID;
+  // L_v must be a sublattice of L (partition of unity on L)
+  for (int c = 0; c < s; ++c) {
+    std::vector<long long> v(s);
+    for (int a = 0; a < s; ++a) v[a] = Lv[a * s + c];
+    if (!on_lattice(lat.adj, lat.det, v)) return LSP_ERR_NOT_ON_LATTICE;
+  }
+  for (int id = 0; id < kNumSpecs; ++id) {
+    const SpecDesc& sd = specs()[id];
+    if (sd.kind != 1 || sd.s != s || sd.vor_n != n || sd.D != lat.D || sd.shifts != lat.shifts) continue;
+    // same Voronoi lattice: equal |det| and every basis vector of either inside the other
+    std::vector<int32_t> slv(s * s);
+    for (int r = 0; r < s; ++r)
+      for (int c = 0; c < s; ++c) slv[r * s + c] = static_cast<int32_t>(sd.vor_lv[r][c]);
+    LatticeShape spec_v;
+    if (!lattice_shape(s, slv.data(), spec_v) || spec_v.det != vlat.det) continue;
+    bool same = true;
+    for (int c = 0; c < s && same; ++c) {
+      std::vector<long long> v(s);
+      for (int a = 0; a < s; ++a) v[a] = Lv[a * s + c];
+      same = on_lattice(spec_v.adj, spec_v.det, v);
+    }
+    if (!same) continue;
+    return make_plan(id, out);
   }
   return LSP_ERR_UNSUPPORTED;
 }
@@ -321,6 +391,8 @@ lsp_status lsp_plan_info(lsp_plan plan, lsp_info* out) {
   out->n_monomials = sd.nmon;
   out->offset_min = sd.omin; out->offset_max = sd.omax;
   std::strncpy(out->name, sd.name, sizeof(out->name) - 1);
+  out->kind = sd.kind;
+  out->voronoi_n = sd.vor_n;
   return LSP_OK;
 }
 

@@ -60,7 +60,9 @@ struct SplitPolicy {
     for (int k = 0; k < SP::K; ++k) t += SP::NNZ[k];
     return t / SP::K;
   }
-  static constexpr bool value = SP::K > 1 && avg_nnz() >= 200;
+  // costly pieces, or many sub-regions (a wave of whole queries would run
+  // most of them): one (query, coset) item per lane, keyed by sub-region
+  static constexpr bool value = SP::K > 1 && (avg_nnz() >= 200 || SP::K >= 8);
 };
 
 template <int S> struct Rec;

@@ -38,6 +38,11 @@ namespace lsp {
 #include "generated/cc_tp4.inc"
 #include "generated/cc_linear_rd.inc"
 #include "generated/bcc_quintic_rd.inc"
+#include "generated/bcc_voronoi1.inc"
+#include "generated/fcc_voronoi1.inc"
+#include "generated/cc_bcc_voronoi1.inc"
+#include "generated/cc_fcc_voronoi1.inc"
+#include "generated/fcc_voronoi2.inc"
 
 constexpr int kMaxCosets = 8;
 constexpr int kMaxDim = 4;

@@ -7,9 +7,20 @@ from workloads import configs as W
 
 SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 10, 10), "c5": (7, 7, 7, 7),
          "d4": (8, 8, 8, 8), "cc_tp2": (20, 20, 20), "cc_tp3": (20, 20, 20), "cc_tp4": (20, 20, 20),
-         "cc_linear_rd": (20, 20, 20), "bcc_quintic_rd": (12, 12, 12)}
+         "cc_linear_rd": (20, 20, 20), "bcc_quintic_rd": (12, 12, 12),
+         "vor_bcc1": (12, 12, 12), "vor_fcc1": (10, 10, 10), "vor_cc_bcc1": (20, 20, 20), "vor_cc_fcc1": (20, 20, 20),
+         "vor_fcc2": (10, 10, 10)}
 NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601, "d4": 401, "cc_tp2": 1301, "cc_tp3": 1301,
-      "cc_tp4": 96, "cc_linear_rd": 1301, "bcc_quintic_rd": 1301}   # cc_tp4: 12 directions make the oracle slow
+      "cc_tp4": 96, "cc_linear_rd": 1301, "bcc_quintic_rd": 1301,   # cc_tp4: 12 directions make the oracle slow
+      "vor_bcc1": 601, "vor_fcc1": 601, "vor_cc_bcc1": 401, "vor_cc_fcc1": 601, "vor_fcc2": 301}
+
+
+def voronoi_oracle(cfg):
+    """The oracle of a Voronoi-spline configuration (the box-spline expansion,
+    pinned against the overlap-volume definition on the CPU)."""
+    from oracle import VoronoiSumOracle
+    return VoronoiSumOracle(cfg.L, cfg.Lv, cfg.voronoi[1], W=cfg.voronoi_gen, sigma=W.VORONOI_SIGMA,
+                            method="boxsum")
 
 
 def small_case(name, n=None, seed=0):
@@ -29,6 +40,15 @@ def small_case(name, n=None, seed=0):
     special[32:40] += rng.integers(0, 2, (8, cfg.s)) * 0.25
     X[-48:] = special
     return cfg, coeffs, X.astype(np.float32)
+
+
+def bf16_round(a):
+    """Values rounded to bfloat16 (nearest, ties to even) through float32, in
+    float64: what a round-to-nearest-even device conversion stores."""
+    b = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def to_dev(arrs, dtype):

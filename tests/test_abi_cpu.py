@@ -77,6 +77,46 @@ def test_plan_errors():
     assert L.status_string(-3).startswith("no generated tables")
 
 
+@pytest.mark.parametrize("name", ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2"])
+def test_voronoi_plan_matches_configs(name):
+    L = _lib()
+    cfg = W.get(name)
+    p = L.lsp_plan_create_voronoi(cfg.L, cfg.Lv, cfg.voronoi[1])
+    info = L.lsp_plan_info(p)
+    assert info["kind"] == "voronoi" and info["voronoi_n"] == cfg.voronoi[1]
+    assert info["lookups"] == cfg.lookups
+    assert info["n_cosets"] == cfg.M and info["D"] == cfg.D
+    L.lsp_plan_destroy(p)
+
+
+def test_voronoi_plan_errors_and_equivalent_bases():
+    L = _lib()
+    # another basis of the BCC lattice, for both L and the cell's lattice
+    Lb = [[2, 0, 1], [0, 2, 1], [0, 0, 1]]
+    p = L.lsp_plan_create_voronoi(Lb, Lb, 1)
+    assert L.lsp_plan_info(p)["name"] == "bcc_voronoi1"
+    L.lsp_plan_destroy(p)
+    with pytest.raises(L.LspError) as e:
+        L.lsp_plan_create_voronoi(W.L_BCC, W.L_CC, 1)        # Z^3 is not inside BCC
+    assert e.value.status == -7
+    with pytest.raises(L.LspError) as e:
+        L.lsp_plan_create_voronoi(W.L_BCC, W.L_BCC, 2)       # BCC V_2: no tables
+    assert e.value.status == -3
+    with pytest.raises(L.LspError) as e:
+        L.lsp_plan_create_voronoi(W.L_CC, [[1, 0, 0], [0, 1, 0], [0, 0, 0]], 1)
+    assert e.value.status == -2
+    with pytest.raises(L.LspError) as e:
+        L.lsp_plan_create_voronoi(W.L_CC, W.L_BCC, 0)
+    assert e.value.status == -2
+    lib = L.lib()
+    assert lib.lsp_plan_create_voronoi(3, None, None, 1, 0, None) == -1
+    # the cell's zonotope generators are not a box spline the library ships
+    gen2 = [[2 * v for v in col] for col in zip(*W.VORONOI_GEN["BCC"])]
+    with pytest.raises(L.LspError) as e:
+        L.lsp_plan_create(W.L_BCC, gen2)
+    assert e.value.status == -3
+
+
 def test_bind_and_eval_argument_errors():
     L = _lib()
     cfg = W.get("c4")
