@@ -59,6 +59,7 @@ typedef int32_t lsp_status;
 #define LSP_ERR_DIMS (-5)          /* coefficient dims out of range */
 #define LSP_ERR_HIP (-6)           /* a HIP runtime call failed */
 #define LSP_ERR_NOT_ON_LATTICE (-7)/* a direction of Xi is not a lattice vector */
+#define LSP_ERR_TOO_LARGE (-8)     /* the input needs more than the library's static scratch */
 
 /* coefficient storage types */
 #define LSP_F32 0
@@ -246,6 +247,23 @@ lsp_status lsp_eval_adjoint_scheduled(lsp_plan plan, lsp_vol vol, const float* x
  * volume's units do not fit in LDS (use lsp_eval_adjoint_scheduled then). */
 lsp_status lsp_mse_backward_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,
                                       size_t ws_bytes, float* const* grad_c, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the binned
+ * forward of lsp_schedule + lsp_eval_scheduled in one call, with the schedule
+ * workspace taken from a static device array of LSP_STATIC_SCRATCH_BYTES
+ * (64 MiB) that each GPU the library runs on holds until the process ends.
+ * Arguments and outputs are those of lsp_eval_scheduled without the workspace;
+ * f and grad_x are written in query order.  LSP_ERR_TOO_LARGE when the
+ * part of the schedule workspace the forward uses (key histograms, records
+ * and per-coset partials: roughly 16-24 bytes per 3-D query plus the key
+ * histograms) exceeds the scratch; nothing is launched then.  Every call on one GPU shares that
+ * GPU's scratch and leaves it holding the last call's schedule: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Allocates nothing. */
+#define LSP_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+lsp_status lsp_eval_scheduled_static(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* f, void* grad_x,
+                                     void* stream);
 
 const char* lsp_status_string(lsp_status status);
 

@@ -17,8 +17,9 @@ EXPORTS = (
     "lsp_plan_create", "lsp_plan_create_voronoi", "lsp_plan_info", "lsp_plan_destroy", "lsp_vol_bind", "lsp_vol_release",
     "lsp_eval", "lsp_eval_mse", "lsp_eval_adjoint", "lsp_eval_rays", "lsp_status_string",
     "lsp_schedule_size", "lsp_schedule", "lsp_eval_scheduled", "lsp_eval_mse_scheduled",
-    "lsp_eval_adjoint_scheduled", "lsp_render", "lsp_mse_backward_scheduled",
+    "lsp_eval_adjoint_scheduled", "lsp_render", "lsp_mse_backward_scheduled", "lsp_eval_scheduled_static",
 )
+LSP_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class LspInfo(ctypes.Structure):
@@ -77,6 +78,7 @@ def lib():
         L.lsp_render.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), i32, i32, i32, i64, i64, vp,
                                  P(LspRenderParams), vp, vp]
         L.lsp_mse_backward_scheduled.argtypes = [vp, vp, vp, i64, vp, sz, P(vp), vp]
+        L.lsp_eval_scheduled_static.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         L.lsp_status_string.argtypes = [i32]
         L.lsp_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -156,6 +158,11 @@ def lsp_vol_release(vol):
 
 def lsp_eval(plan, vol, x_ptr, n, f_ptr, grad_ptr, stream):
     check(lib().lsp_eval(plan, vol, x_ptr, int(n), f_ptr, grad_ptr, stream), "lsp_eval")
+
+
+def lsp_eval_scheduled_static(plan, vol, x_ptr, n, f_ptr, grad_ptr, stream):
+    check(lib().lsp_eval_scheduled_static(plan, vol, x_ptr, int(n), f_ptr, grad_ptr, stream),
+          "lsp_eval_scheduled_static")
 
 
 def lsp_eval_mse(plan, vol, x_ptr, y_ptr, n, f_ptr, dldf_ptr, dldx_ptr, loss_ptr, stream):

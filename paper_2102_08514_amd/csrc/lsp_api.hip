@@ -278,6 +278,7 @@ const char* lsp_status_string(lsp_status s) {
     case LSP_ERR_DIMS: return "coefficient dims out of range";
     case LSP_ERR_HIP: return "HIP runtime error";
     case LSP_ERR_NOT_ON_LATTICE: return "a direction of Xi is not a lattice vector";
+    case LSP_ERR_TOO_LARGE: return "the input needs more than the static scratch (LSP_STATIC_SCRATCH_BYTES)";
   }
   return "unknown status";
 }
@@ -572,6 +573,58 @@ lsp_status lsp_schedule(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, v
     return st;
   sched_record(workspace, sched_key(plan, vol, x, n));
   return LSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free schedule + evaluation: the workspace is `scratch`, a static
+// device array.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device, and is kept
+// per device (every GPU holds its own copy of the array).
+static __device__ __align__(256) unsigned char scratch[LSP_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current)
+lsp_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LSP_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LSP_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LSP_OK;
+}
+}  // namespace
+
+static lsp_status static_need(lsp_plan plan, lsp_vol vol, int64_t n, size_t* bytes) {
+  LSP_DISPATCH(plan->spec, sched_fwd_size_spec, vol, n, bytes)
+}
+
+lsp_status lsp_eval_scheduled_static(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, void* f, void* grad_x,
+                                     void* stream) {
+  lsp_status st = check_pv(plan, vol);
+  if (st != LSP_OK) return st;
+  if (n < 0) return LSP_ERR_INVALID;
+  if (n == 0) return LSP_OK;
+  if (!x || !f) return LSP_ERR_NULL;
+  if (n * specs()[plan->spec].M >= (int64_t(1) << 32)) return LSP_ERR_INVALID;
+  size_t need = 0;
+  if ((st = static_need(plan, vol, n, &need)) != LSP_OK) return st;
+  if (need > LSP_STATIC_SCRATCH_BYTES) return LSP_ERR_TOO_LARGE;
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws)) != LSP_OK) return st;
+  // the schedule writes every word of the workspace it later reads (key
+  // histograms, scans, records, partials), so nothing needs clearing first
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = dispatch_schedule(plan, vol, x, n, ws, s)) != LSP_OK) return st;
+  LSP_DISPATCH(plan->spec, eval_spec, vol, x, n, ws, f, grad_x, s)
 }
 
 lsp_status lsp_eval_scheduled(lsp_plan plan, lsp_vol vol, const float* x, int64_t n, const void* workspace,

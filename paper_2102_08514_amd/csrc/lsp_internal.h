@@ -36,6 +36,8 @@ lsp_status adj_spec(const lsp_vol_s* v, const float* x, const float* g, int64_t 
 template <class SP>
 lsp_status sched_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes);
 template <class SP>
+lsp_status sched_fwd_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes);
+template <class SP>
 lsp_status sched_spec(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st);
 template <class SP>
 lsp_status rays_spec(const lsp_vol_s* v, const lsp::RayParams& rp, int64_t ray0, int64_t nrays, float* out,

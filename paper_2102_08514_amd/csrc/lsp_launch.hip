@@ -329,6 +329,14 @@ lsp_status sched_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes) {
   return LSP_OK;
 }
 
+// bytes of the workspace the schedule and the forward use: the layout up to
+// the adjoint's per-unit regions (key histograms, scans, records, partials)
+template <class SP>
+lsp_status sched_fwd_size_spec(const lsp_vol_s* v, int64_t n, size_t* bytes) {
+  *bytes = make_bin<SP>(v, n).off_priv;
+  return LSP_OK;
+}
+
 template <class SP>
 lsp_status sched_spec(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
   return run_schedule<SP>(v, x, n, ws, st);
@@ -397,6 +405,7 @@ lsp_status render_spec(const lsp_vol_s* v, const RayParams& rp, const RenderPara
   template lsp_status adj_spec<SP>(const lsp_vol_s*, const float*, const float*, int64_t, const void*,           \
                                    float* const*, float*, hipStream_t, bool);                                   \
   template lsp_status sched_size_spec<SP>(const lsp_vol_s*, int64_t, size_t*);                                  \
+  template lsp_status sched_fwd_size_spec<SP>(const lsp_vol_s*, int64_t, size_t*);                              \
   template lsp_status sched_spec<SP>(const lsp_vol_s*, const float*, int64_t, void*, hipStream_t);               \
   template lsp_status rays_spec<SP>(const lsp_vol_s*, const RayParams&, int64_t, int64_t, float*, float*,        \
                                     hipStream_t);                                                               \
