@@ -483,10 +483,8 @@ __device__ __forceinline__ int unit_shift(unsigned items, float gmax) {
 // one coset's psi (and folded gradient mapped back to x) from LDS or global.
 // region: the LDS copy of coset k's part of the unit's region (or null).
 template <class SP, class CT, class AT, bool GRAD, bool STAGE>
-__device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP, AT>& si, const AT* region, int k,
-                                             const AT* xq, AT& f, AT* gx) {
-  Folded<SP, AT> F;
-  fold_query<SP, AT>(xq, k, vol, F);
+__device__ __forceinline__ void coset_binned_folded(const Vol& vol, const StageInfo<SP, AT>& si, const AT* region,
+                                                    int k, const Folded<SP, AT>& F, AT& f, AT* gx) {
   const int ob = SP::template orbit<AT>(F.up);
   AT b[SP::NMON];
   bool staged = false;
@@ -508,14 +506,15 @@ __device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP,
   monomials<SP, AT>(F.up, ob, mono);
   AT dpsi[SP::S];
   f += poly_eval<SP, AT, GRAD>(b, mono, dpsi);
-  if constexpr (GRAD) {
-#pragma unroll
-    for (int r = 0; r < SP::S; ++r) {
-      const AT v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
-#pragma unroll
-      for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : AT(0);
-    }
-  }
+  if constexpr (GRAD) unfold_grad<SP, AT>(F, dpsi, gx);
+}
+
+template <class SP, class CT, class AT, bool GRAD, bool STAGE>
+__device__ __forceinline__ void coset_binned(const Vol& vol, const StageInfo<SP, AT>& si, const AT* region, int k,
+                                             const AT* xq, AT& f, AT* gx) {
+  Folded<SP, AT> F;
+  fold_query<SP, AT>(xq, k, vol, F);
+  coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, region, k, F, f, gx);
 }
 
 struct UnitRange {
@@ -597,9 +596,17 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
         for (int d = 0; d < SP::S; ++d) grad[slot * SP::S + d] = gx[d];
       }
     } else {
+      if constexpr (complement_coset<SP>()) {
+        Folded<SP, AT> F0, F1;
+        fold_query<SP, AT>(xq, 0, vol, F0);
+        coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, lds, 0, F0, acc, gx);
+        fold_complement<SP, AT>(F0, vol, F1);
+        coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, lds + si.vol, 1, F1, acc, gx);
+      } else {
 #pragma unroll
-      for (int kk = 0; kk < SP::M; ++kk)
-        coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds + kk * si.vol, kk, xq, acc, gx);
+        for (int kk = 0; kk < SP::M; ++kk)
+          coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds + kk * si.vol, kk, xq, acc, gx);
+      }
       if (f) f[q] = acc;    // optional for the MSE head
       AT scale = AT(1);
       if constexpr (MSE) {
@@ -756,12 +763,7 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
         }
         float dpsi[SP::S];
         (void)poly_eval<SP, float, true>(b, mono, dpsi);
-#pragma unroll
-        for (int r = 0; r < SP::S; ++r) {
-          const float v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
-#pragma unroll
-          for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : 0.f;
-        }
+        unfold_grad<SP, float>(F, dpsi, gx);
       }
     }
     if constexpr (GRADX) {

@@ -102,6 +102,7 @@ struct Folded {
   int ax[SP::S];      // folded axis r comes from original axis ax[r]
   int sg[SP::S];      // and carries sign sg[r]: up[r] = sg[r] * u[ax[r]]
   int pi[SP::S];      // cell index along original axis ax[r]
+  int neg;            // bit d: u[d] < 0 (original axis d)
   bool interior;      // the whole stencil lies inside the stored arrays
 };
 
@@ -150,6 +151,7 @@ __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, F
   constexpr int S = SP::S;
   AT a[S];
   bool interior = true;
+  int neg = 0;
 #pragma unroll
   for (int d = 0; d < S; ++d) {
     AT xp = x[d] - AT(coset_shift<SP>(k, d));
@@ -164,7 +166,9 @@ __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, F
     a[d] = u;
     F.ax[d] = d;
     F.sg[d] = (u >= AT(0)) ? 1 : -1;
+    neg |= (u < AT(0)) ? (1 << d) : 0;
   }
+  F.neg = neg;
   F.interior = interior;
   AT v[S];
 #pragma unroll
@@ -186,6 +190,42 @@ __device__ __forceinline__ void fold_query(const AT* x, int k, const Vol& vol, F
   }
 #pragma unroll
   for (int d = 0; d < S; ++d) F.up[d] = v[d];
+}
+
+// The second coset of D Z^s u (D Z^s + (1,...,1)) with D = 2 (BCC; the B
+// fold): per axis, u_1 = u_0 - 1 when u_0 >= 0 (same cell) and u_0 + 1 when
+// u_0 < 0 (the cell below), so |u_1| = 1 - |u_0| and the sign flips.  The
+// descending order of |u_1| is that of |u_0| reversed: coset 1's fold is read
+// off coset 0's instead of recomputed.  Exact for |x| >= 1 (|u_0| is then a
+// multiple of a power of two no finer than 2^-23).
+template <class SP>
+constexpr bool complement_coset() {
+  if (SP::M != 2 || SP::D != 2 || SP::FOLD_D) return false;
+  for (int d = 0; d < SP::S; ++d)
+    if (SP::SHIFT[1][d] != 1) return false;
+  return true;
+}
+
+template <class SP, class AT>
+__device__ __forceinline__ void fold_complement(const Folded<SP, AT>& F0, const Vol& vol, Folded<SP, AT>& F1) {
+  constexpr int S = SP::S;
+  bool interior = true;
+#pragma unroll
+  for (int d = 0; d < S; ++d) {
+    const int id = F0.i[d] - ((F0.neg >> d) & 1);
+    F1.i[d] = id;
+    interior = interior && (id + SP::OMIN >= 0) && (id + SP::OMAX < vol.dims[d]);
+  }
+  F1.interior = interior;
+  F1.neg = ~F0.neg & ((1 << S) - 1);
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    F1.up[r] = AT(1) - F0.up[S - 1 - r];
+    F1.ax[r] = F0.ax[S - 1 - r];
+    F1.sg[r] = -F0.sg[S - 1 - r];
+    // cell index along axis ax[r]: one lower where u_0 < 0 there (sg_0 < 0)
+    F1.pi[r] = F0.pi[S - 1 - r] - (F0.sg[S - 1 - r] < 0 ? 1 : 0);
+  }
 }
 
 // Gather through the fold: folded site J maps to original offset
@@ -358,11 +398,26 @@ __device__ __forceinline__ AT poly_eval(const AT* b, const AT* mono, AT* dpsi) {
   return psi;
 }
 
-// one coset's contribution (value, and gradient in the original frame)
+// folded-frame gradient back to the original frame: up[r] = sg[r] u[ax[r]],
+// so d/du[ax[r]] = sg[r] d/dup[r]
+template <class SP, class AT>
+__device__ __forceinline__ void unfold_grad(const Folded<SP, AT>& F, const AT* dpsi, AT* gx) {
+  AT w[SP::S];
+#pragma unroll
+  for (int r = 0; r < SP::S; ++r) w[r] = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) {
+    AT v = w[SP::S - 1];
+#pragma unroll
+    for (int r = SP::S - 2; r >= 0; --r) v = (F.ax[r] == d) ? w[r] : v;
+    gx[d] += v;
+  }
+}
+
+// one coset's contribution (value, and gradient in the original frame) from
+// its folded geometry
 template <class SP, class CT, class AT, bool GRAD>
-__device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* xq, AT& f, AT* gx) {
-  Folded<SP, AT> F;
-  fold_query<SP, AT>(xq, k, vol, F);
+__device__ __forceinline__ void coset_contrib_folded(const Vol& vol, int k, const Folded<SP, AT>& F, AT& f, AT* gx) {
   const int ob = SP::template orbit<AT>(F.up);
   AT b[SP::NMON];
   if (F.interior && vol.bytes32) {
@@ -382,14 +437,28 @@ __device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* x
   monomials<SP, AT>(F.up, ob, mono);
   AT dpsi[SP::S];
   f += poly_eval<SP, AT, GRAD>(b, mono, dpsi);
-  if constexpr (GRAD) {
+  if constexpr (GRAD) unfold_grad<SP, AT>(F, dpsi, gx);
+}
+
+template <class SP, class CT, class AT, bool GRAD>
+__device__ __forceinline__ void coset_contrib(const Vol& vol, int k, const AT* xq, AT& f, AT* gx) {
+  Folded<SP, AT> F;
+  fold_query<SP, AT>(xq, k, vol, F);
+  coset_contrib_folded<SP, CT, AT, GRAD>(vol, k, F, f, gx);
+}
+
+// every coset of one query (Algorithm 1, outer loop)
+template <class SP, class CT, class AT, bool GRAD>
+__device__ __forceinline__ void all_cosets(const Vol& vol, const AT* xq, AT& f, AT* gx) {
+  if constexpr (complement_coset<SP>()) {
+    Folded<SP, AT> F0, F1;
+    fold_query<SP, AT>(xq, 0, vol, F0);
+    coset_contrib_folded<SP, CT, AT, GRAD>(vol, 0, F0, f, gx);
+    fold_complement<SP, AT>(F0, vol, F1);
+    coset_contrib_folded<SP, CT, AT, GRAD>(vol, 1, F1, f, gx);
+  } else {
 #pragma unroll
-    for (int r = 0; r < SP::S; ++r) {
-      // up[r] = sg[r] * u[ax[r]]  =>  d/du[ax[r]] = sg[r] * d/dup[r]
-      const AT v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
-#pragma unroll
-      for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : AT(0);
-    }
+    for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, AT, GRAD>(vol, k, xq, f, gx);
   }
 }
 
@@ -426,12 +495,7 @@ __device__ __forceinline__ void coset_adjoint(const Vol& vol, const GradVol& gvo
     }
     float dpsi[SP::S];
     (void)poly_eval<SP, float, true>(b, mono, dpsi);
-#pragma unroll
-    for (int r = 0; r < SP::S; ++r) {
-      const float v = F.sg[r] > 0 ? dpsi[r] : -dpsi[r];
-#pragma unroll
-      for (int d = 0; d < SP::S; ++d) gx[d] += (F.ax[r] == d) ? v : 0.f;
-    }
+    unfold_grad<SP, float>(F, dpsi, gx);
   }
 }
 
@@ -478,8 +542,7 @@ __global__ void __launch_bounds__(256) k_eval(Vol vol, const float* __restrict__
       for (int d = 0; d < SP::S; ++d) atomicAdd(grad + q * SP::S + d, gx[d]);
     }
   } else {
-#pragma unroll
-    for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, AT, GRAD>(vol, kk, xq, acc, gx);
+    all_cosets<SP, CT, AT, GRAD>(vol, xq, acc, gx);
     f[q] = acc;
     if constexpr (GRAD) {
 #pragma unroll
@@ -520,8 +583,7 @@ __global__ void __launch_bounds__(256) k_eval_mse(Vol vol, const float* __restri
     float gx[SP::S];
 #pragma unroll
     for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
-#pragma unroll
-    for (int kk = 0; kk < SP::M; ++kk) coset_contrib<SP, CT, float, GRAD>(vol, kk, xq, acc, gx);
+    all_cosets<SP, CT, float, GRAD>(vol, xq, acc, gx);
     const float r = acc - y[q];
     const float dl = 2.f * r * inv_n;
     if (f) f[q] = acc;      // optional
@@ -688,8 +750,7 @@ __global__ void __launch_bounds__(256) k_rays(Vol vol, RayParams rp, long long r
     for (int a = 0; a < 3; ++a) xq[a] = __fadd_rn(base[a], __fmul_rn(rp.A[3 * a + 2], tj));
     float f = 0.f;
     float gx[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, float, true>(vol, k, xq, f, gx);
+    all_cosets<SP, CT, float, true>(vol, xq, f, gx);
     sf += f; sg0 += gx[0]; sg1 += gx[1]; sg2 += gx[2];
     if (samples) {
       float* o = samples + (t * rp.steps + j) * 4;
@@ -747,8 +808,7 @@ __global__ void __launch_bounds__(256) k_render(Vol vol, RayParams rp, RenderPar
     for (int a = 0; a < 3; ++a) xq[a] = __fadd_rn(base[a], __fmul_rn(rp.A[3 * a + 2], tj));
     float f = 0.f;
     float gx[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < SP::M; ++k) coset_contrib<SP, CT, float, true>(vol, k, xq, f, gx);
+    all_cosets<SP, CT, float, true>(vol, xq, f, gx);
     float sidx = (f - rd.f0) * tscale;
     sidx = fminf(fmaxf(sidx, 0.f), tmax);       // also maps NaN to 0
     const int i = min(static_cast<int>(sidx), rd.tf_len - 2);
