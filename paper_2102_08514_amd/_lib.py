@@ -8,7 +8,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "lib", "liblsp.so")
+# LSP_LIBRARY selects another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree one
+LIB_PATH = os.environ.get("LSP_LIBRARY") or os.path.join(_PKG, "lib", "liblsp.so")
 
 LSP_F32, LSP_BF16, LSP_F16, LSP_F64 = 0, 1, 2, 3
 
