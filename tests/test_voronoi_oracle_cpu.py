@@ -95,7 +95,7 @@ def test_partition_of_unity_and_linear_precision(name):
     o = VoronoiSumOracle(cfg.L, cfg.Lv, cfg.voronoi[1], W=cfg.voronoi_gen, sigma=W.VORONOI_SIGMA)
     dims = (12, 12, 12)
     D = cfg.D
-    X = RNG.uniform(D * 5, D * 6 + 1, (12 if cfg.voronoi[1] == 2 else 40, 3))
+    X = RNG.uniform(D * 5, D * 6 + 1, (4 if cfg.voronoi[1] == 2 else 12 if D == 1 else 30, 3))
     X[:6] = np.floor(2 * X[:6]) / 2           # lattice sites and half-integers: planes of V and V + w coincide
     ones = [np.ones(dims) for _ in range(cfg.M)]
     assert np.max(np.abs(o.eval(ones, X) - 1)) < 1e-12
