@@ -45,8 +45,11 @@ WORKLOADS = {
     "c4": "FCC 4x128^3, 6-direction box spline, 2^22 queries, MSE forward + backward",
     "c5": "D4* 2x48^4, 8-direction box spline, 2^22 queries, MSE forward + backward",
     "d4": "D4 8x24^4, the 8-direction box spline of Sec. 5.2 (240 lookups), 2^22 queries, forward",
+    "vor_rays": "BCC 2x192^3, BCC Voronoi spline 1, 1024x1024 rays x 512 steps, forward + grad",
+    "vor_fcc": "FCC 4x128^3, FCC Voronoi spline 1, 2^22 random queries, forward",
 }
-SUB_RECORDS = (("c2", "bf16"), ("c3", "f32"), ("c3", "bf16"), ("c4", "f32"), ("c5", "f32"), ("c5", "bf16"))
+SUB_RECORDS = (("c2", "bf16"), ("c3", "f32"), ("c3", "bf16"), ("c4", "f32"), ("c5", "f32"), ("c5", "bf16"),
+               ("vor_rays", "f32"), ("vor_fcc", "f32"))
 ACC_PREFIX = {"c2": 4096, "c4": 4096, "c5": 2048, "d4": 512, "c1": 100000}
 
 
@@ -55,13 +58,19 @@ def log(*a):
 
 
 # ------------------------------------------------------------------ CPU oracle
+def make_oracle(cfg):
+    from oracle import ConvolutionSumOracle, VoronoiSumOracle
+    from workloads import configs as W
+    if cfg.voronoi:
+        return VoronoiSumOracle(cfg.L, cfg.Lv, cfg.voronoi[1], W=cfg.voronoi_gen, sigma=W.VORONOI_SIGMA,
+                                method="boxsum")
+    return ConvolutionSumOracle(cfg.L, cfg.Xi)
+
+
 def _oracle_chunk(args):
     name, coeffs, X, chunk, grad = args
-    from oracle import ConvolutionSumOracle
     from workloads import configs as W
-    cfg = W.get(name)
-    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
-    return o.eval(coeffs, X, chunk=chunk, want_grad=grad)
+    return make_oracle(W.get(name)).eval(coeffs, X, chunk=chunk, want_grad=grad)
 
 
 def host_cores():
@@ -158,7 +167,7 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
 _CSRC = "paper_2102_08514_amd/csrc"
 _SHARED_SRC = ("lsp_kernels.hip", "lsp_binned.hip", "lsp_launch.hip", "lsp_internal.h", "lsp_api.hip")
 SPLINE_OF = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir",
-             "d4": "d4_8dir"}
+             "d4": "d4_8dir", "vor_rays": "bcc_voronoi1", "vor_fcc": "fcc_voronoi1"}
 
 
 def kernel_source_digest(config=None):
@@ -268,13 +277,15 @@ class Workload:
         self.bytes_c = {torch.float32: 4, torch.bfloat16: 2, torch.float16: 2, torch.float64: 8}[tdt]
         log(f"[bench] generating {name} inputs ({self.dname})")
         self.coeffs = I.coefficients(cfg)
-        self.sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+        self.sp = (lsp.LatticeSpline(cfg.L, voronoi=(cfg.Lv, cfg.voronoi[1])) if cfg.voronoi else
+                   lsp.LatticeSpline(cfg.L, cfg.Xi))
         self.info = self.sp.info
         self.dev = [torch.from_numpy(np.ascontiguousarray(c)).to(tdt).cuda() for c in self.coeffs]
         self.vol = self.sp.bind(self.dev)
         self.strm = torch.cuda.current_stream().cuda_stream
         self.s = cfg.s
-        self.X = None if name == "c3" else I.queries(cfg)
+        self.rays = "rays" in cfg.extra
+        self.X = None if self.rays else I.queries(cfg)
         self.I = I
 
     def stored(self):
@@ -455,7 +466,7 @@ def run_workload(name, dtype, args, torch, lsp, W, I, headline=False):
            "lookups_per_sample": w.info["lookups"], "volume_dims": list(w.cfg.dims), "n_cosets": w.cfg.M,
            "passes": w.cfg.passes}
     t0 = time.perf_counter()
-    if name == "c3":
+    if w.rays:
         r = bench_rays(w, args.steps, args.warmup, render=args.render)
     elif w.cfg.passes == "mse":
         r = bench_mse(w, args.steps, args.warmup, order=args.order)
@@ -475,7 +486,7 @@ def run_workload(name, dtype, args, torch, lsp, W, I, headline=False):
     rec.update(r)
     # accuracy against the FP64 oracle
     if not args.no_acc:
-        if name == "c3":
+        if w.rays:
             got, P = rays_accuracy(w)
             fw, gw = oracle_values(name, w.stored(), P, grad=True)
             rec["accuracy"] = error_record(got[:, 0], fw, w.coeffs, "stored coefficients, every sample of 3 rays")
@@ -544,7 +555,7 @@ def main():
         "config": {"workload": head["workload"], "spline": head["spline"], "n_samples": head["n_samples"],
                    "lookups_per_sample": head["lookups_per_sample"], "volume_dims": head["volume_dims"],
                    "n_cosets": head["n_cosets"], "passes": head["passes"],
-                   "order": ("render" if args.render else "rays") if name == "c3" else args.order},
+                   "order": ("render" if args.render else "rays") if "rays" in W.get(name).extra else args.order},
     }
     ph = head.pop("roofline")
     rec["roofline"] = ph["forward"] if isinstance(ph, dict) and "forward" in ph else ph

@@ -147,6 +147,15 @@ CONFIGS = {
     "vor_fcc2": Config("vor_fcc2", "FCC 4x32^3, FCC Voronoi spline 2", L_FCC, None, 2,
                        (_z(3), (1, 1, 0), (1, 0, 1), (0, 1, 1)), (32, 32, 32), 1 << 20, 4.0, 59.0, "uniform",
                        lookups=27, voronoi=("FCC", 2)),
+    # Voronoi splines at benchmark size: the c3 ray grid on a BCC volume, and
+    # c4's FCC volume under random queries
+    "vor_rays": Config("vor_rays", "BCC 2x192^3, BCC Voronoi spline 1, 1024x1024 rays x 512 steps, forward + grad",
+                       L_BCC, None, 2, (_z(3), (1, 1, 1)), (192, 192, 192), 1 << 29, 4.0, 379.0,
+                       "field", noise=0.01, passes="fwd+grad", lookups=8, extra={"rays": (1024, 1024), "steps": 512},
+                       voronoi=("BCC", 1)),
+    "vor_fcc": Config("vor_fcc", "FCC 4x128^3, FCC Voronoi spline 1, 2^22 random queries, forward",
+                      L_FCC, None, 2, (_z(3), (1, 1, 0), (1, 0, 1), (0, 1, 1)), (128, 128, 128), 1 << 22,
+                      3.0, 252.0, "field", lookups=8, voronoi=("FCC", 1)),
 }
 
 
