@@ -113,7 +113,7 @@ lsp_status lsp_plan_create(int32_t s, const int32_t* L, int32_t n, const int32_t
  * least as close to the origin as to any other site of Lv) and V_n =
  * V_0 * V_{n-1} (Sec. 3, Voronoi splines).  phi is a partition of unity on L
  * because Lv is a sublattice of L.  Shipped: BCC and FCC V_1 on their own
- * lattices and on Z^3, FCC V_2 on FCC (Table 1's Voronoi rows).  Lv is
+ * lattices and on Z^3, FCC V_2 on FCC and on Z^3 (Table 1's Voronoi rows).  Lv is
  * matched as a lattice (any basis).  Errors: LSP_ERR_NULL, LSP_ERR_INVALID
  * (singular L or Lv, n < 1), LSP_ERR_NOT_ON_LATTICE (Lv not inside L),
  * LSP_ERR_UNSUPPORTED (no tables).  flags: reserved, pass 0. */

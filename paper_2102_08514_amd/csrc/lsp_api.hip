@@ -22,7 +22,7 @@ using namespace lsp;
 enum SpecId {
   kBccLinear = 0, kCcZp, kBccQuartic, kFcc6, kD4s8, kD48,
   kCcTp2, kCcTp3, kCcTp4, kCcLinearRd, kBccQuinticRd,
-  kBccVoronoi1, kFccVoronoi1, kCcBccVoronoi1, kCcFccVoronoi1, kFccVoronoi2, kNumSpecs
+  kBccVoronoi1, kFccVoronoi1, kCcBccVoronoi1, kCcFccVoronoi1, kFccVoronoi2, kCcFccVoronoi2, kNumSpecs
 };
 
 struct SpecDesc {
@@ -74,7 +74,7 @@ const std::vector<SpecDesc>& specs() {
       describe<SplineCcLinearRd>("cc_linear_rd"), describe<SplineBccQuinticRd>("bcc_quintic_rd"),
       describe<SplineBccVoronoi1>("bcc_voronoi1"), describe<SplineFccVoronoi1>("fcc_voronoi1"),
       describe<SplineCcBccVoronoi1>("cc_bcc_voronoi1"), describe<SplineCcFccVoronoi1>("cc_fcc_voronoi1"),
-      describe<SplineFccVoronoi2>("fcc_voronoi2")};
+      describe<SplineFccVoronoi2>("fcc_voronoi2"), describe<SplineCcFccVoronoi2>("cc_fcc_voronoi2")};
   return all;
 }
 
@@ -261,6 +261,7 @@ bool sched_matches(const void* ws, const SchedKey& k) {
     case kCcBccVoronoi1: return lsp_host::FN<SplineCcBccVoronoi1>(__VA_ARGS__); \
     case kCcFccVoronoi1: return lsp_host::FN<SplineCcFccVoronoi1>(__VA_ARGS__); \
     case kFccVoronoi2: return lsp_host::FN<SplineFccVoronoi2>(__VA_ARGS__); \
+    case kCcFccVoronoi2: return lsp_host::FN<SplineCcFccVoronoi2>(__VA_ARGS__); \
   }                                                                   \
   return LSP_ERR_UNSUPPORTED;
 

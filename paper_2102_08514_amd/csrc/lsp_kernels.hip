@@ -43,6 +43,7 @@ namespace lsp {
 #include "generated/cc_bcc_voronoi1.inc"
 #include "generated/cc_fcc_voronoi1.inc"
 #include "generated/fcc_voronoi2.inc"
+#include "generated/cc_fcc_voronoi2.inc"
 
 constexpr int kMaxCosets = 8;
 constexpr int kMaxDim = 4;

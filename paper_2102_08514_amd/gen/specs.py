@@ -58,6 +58,7 @@ SPECS = {
     "cc_bcc_voronoi1": ("SplineCcBccVoronoi1", L_CC, VoronoiSpec(L_BCC, W_BCC_CELL, 2, 1)),
     "cc_fcc_voronoi1": ("SplineCcFccVoronoi1", L_CC, VoronoiSpec(L_FCC, W_FCC_CELL, 2, 1)),
     "fcc_voronoi2": ("SplineFccVoronoi2", L_FCC, VoronoiSpec(L_FCC, W_FCC_CELL, 2, 2)),
+    "cc_fcc_voronoi2": ("SplineCcFccVoronoi2", L_CC, VoronoiSpec(L_FCC, W_FCC_CELL, 2, 2)),
 }
 
 

@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.dirname(HERE))
 
-NAMES = ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2"]
+NAMES = ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2", "vor_cc_fcc2"]
 OUT = os.path.join(HERE, "voronoi_expected.npz")
 
 
@@ -45,11 +45,17 @@ def job(args):
     return {"adj": np.stack(o.adjoint(X64, g, dims)), "adj_abs": np.stack(o.adjoint(X64, np.abs(g), dims))}
 
 
-def main():
-    jobs = [(n, p) for n in NAMES for p in ("f", "bf16", "adj")]
+def main(names=None):
+    """Regenerate the given workloads (all by default), keeping the others'
+    stored values."""
+    names = names or NAMES
+    jobs = [(n, p) for n in names for p in ("f", "bf16", "adj")]
     with Pool(min(len(jobs), os.cpu_count() or 1)) as pool:
         res = pool.map(job, jobs)
     out = {}
+    if os.path.exists(OUT):
+        with np.load(OUT, allow_pickle=False) as z:
+            out = {k: z[k] for k in z.files if k.split("/")[0] not in names}
     for (name, _), r in zip(jobs, res):
         for k, v in r.items():
             out[f"{name}/{k}"] = np.asarray(v, dtype=np.float64)
@@ -58,4 +64,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

@@ -9,10 +9,10 @@ SMALL = {"c1": (12, 12, 12), "c2": (20, 20, 20), "c3": (12, 12, 12), "c4": (10, 
          "d4": (8, 8, 8, 8), "cc_tp2": (20, 20, 20), "cc_tp3": (20, 20, 20), "cc_tp4": (20, 20, 20),
          "cc_linear_rd": (20, 20, 20), "bcc_quintic_rd": (12, 12, 12),
          "vor_bcc1": (12, 12, 12), "vor_fcc1": (10, 10, 10), "vor_cc_bcc1": (20, 20, 20), "vor_cc_fcc1": (20, 20, 20),
-         "vor_fcc2": (10, 10, 10)}
+         "vor_fcc2": (10, 10, 10), "vor_cc_fcc2": (14, 14, 14)}
 NQ = {"c1": 1301, "c2": 1301, "c3": 1301, "c4": 1301, "c5": 601, "d4": 401, "cc_tp2": 1301, "cc_tp3": 1301,
       "cc_tp4": 96, "cc_linear_rd": 1301, "bcc_quintic_rd": 1301,   # cc_tp4: 12 directions make the oracle slow
-      "vor_bcc1": 601, "vor_fcc1": 601, "vor_cc_bcc1": 401, "vor_cc_fcc1": 601, "vor_fcc2": 301}
+      "vor_bcc1": 601, "vor_fcc1": 601, "vor_cc_bcc1": 401, "vor_cc_fcc1": 601, "vor_fcc2": 301, "vor_cc_fcc2": 201}
 
 
 def voronoi_oracle(cfg):

@@ -77,7 +77,7 @@ def test_plan_errors():
     assert L.status_string(-3).startswith("no generated tables")
 
 
-@pytest.mark.parametrize("name", ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2"])
+@pytest.mark.parametrize("name", ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2", "vor_cc_fcc2"])
 def test_voronoi_plan_matches_configs(name):
     L = _lib()
     cfg = W.get(name)

@@ -15,7 +15,7 @@ from paper_2102_08514_amd.gen.tables import GENERATED, load
 
 NAMES = ["bcc_linear", "cc_zp", "bcc_quartic", "fcc_6dir", "d4s_8dir", "d4_8dir", "cc_tp2", "cc_tp3", "cc_tp4",
          "cc_linear_rd", "bcc_quintic_rd", "bcc_voronoi1", "fcc_voronoi1", "cc_bcc_voronoi1", "cc_fcc_voronoi1",
-         "fcc_voronoi2"]
+         "fcc_voronoi2", "cc_fcc_voronoi2"]
 
 
 def _functions(text):

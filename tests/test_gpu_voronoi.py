@@ -23,9 +23,9 @@ from workloads import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-VOR = ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2"]
+VOR = ["vor_bcc1", "vor_fcc1", "vor_cc_bcc1", "vor_cc_fcc1", "vor_fcc2", "vor_cc_fcc2"]
 TABLE = {"vor_bcc1": "bcc_voronoi1", "vor_fcc1": "fcc_voronoi1", "vor_cc_bcc1": "cc_bcc_voronoi1",
-         "vor_cc_fcc1": "cc_fcc_voronoi1", "vor_fcc2": "fcc_voronoi2"}
+         "vor_cc_fcc1": "cc_fcc_voronoi1", "vor_fcc2": "fcc_voronoi2", "vor_cc_fcc2": "cc_fcc_voronoi2"}
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "voronoi_expected.npz")
 _EXP = {}
 

@@ -21,7 +21,8 @@ from workloads import configs as W
 NAMES = {"c1": "bcc_linear", "c2": "cc_zp", "c3": "bcc_quartic", "c4": "fcc_6dir", "c5": "d4s_8dir", "d4": "d4_8dir",
          "cc_tp2": "cc_tp2", "cc_tp3": "cc_tp3", "cc_tp4": "cc_tp4", "cc_linear_rd": "cc_linear_rd",
          "bcc_quintic_rd": "bcc_quintic_rd", "vor_bcc1": "bcc_voronoi1", "vor_fcc1": "fcc_voronoi1",
-         "vor_cc_bcc1": "cc_bcc_voronoi1", "vor_cc_fcc1": "cc_fcc_voronoi1", "vor_fcc2": "fcc_voronoi2"}
+         "vor_cc_bcc1": "cc_bcc_voronoi1", "vor_cc_fcc1": "cc_fcc_voronoi1", "vor_fcc2": "fcc_voronoi2",
+         "vor_cc_fcc2": "cc_fcc_voronoi2"}
 
 
 def oracle_for(cfg):

@@ -147,6 +147,8 @@ CONFIGS = {
     "vor_fcc2": Config("vor_fcc2", "FCC 4x32^3, FCC Voronoi spline 2", L_FCC, None, 2,
                        (_z(3), (1, 1, 0), (1, 0, 1), (0, 1, 1)), (32, 32, 32), 1 << 20, 4.0, 59.0, "uniform",
                        lookups=27, voronoi=("FCC", 2)),
+    "vor_cc_fcc2": Config("vor_cc_fcc2", "Z^3 32^3, FCC Voronoi spline 2 on the Cartesian lattice", L_CC, None, 1,
+                          (_z(3),), (32, 32, 32), 1 << 20, 3.0, 28.0, "uniform", lookups=54, voronoi=("FCC", 2)),
     # Voronoi splines at benchmark size: the c3 ray grid on a BCC volume, and
     # c4's FCC volume under random queries
     "vor_rays": Config("vor_rays", "BCC 2x192^3, BCC Voronoi spline 1, 1024x1024 rays x 512 steps, forward + grad",
