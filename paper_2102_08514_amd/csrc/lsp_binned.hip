@@ -12,7 +12,9 @@
 //      every (tile, key) sub-run in the key-sorted order;
 //   3. k_bin_place  per tile, LDS cursors place each item's record
 //      (query coordinates + item id) at its sorted position; a tile's items of
-//      one key land contiguously;
+//      one key land contiguously.  For 3-D splines with few keys
+//      k_bin_place_win first sorts windows of the tile by key in LDS, so that
+//      each key's records of a window leave as one contiguous run;
 //   4. k_eval_binned: one workgroup per unit (a brick, or a (brick, coset)
 //      pair for coset-split items) stages the unit's coefficients (plus the
 //      stencil halo, zero outside the volume) into LDS with coalesced loads,
@@ -232,6 +234,155 @@ __global__ void __launch_bounds__(1024) k_bin_place(Vol vol, BinGeom g, const fl
       }
       recs[pos[u]] = r;
     }
+  }
+}
+
+template <class SP>
+__device__ __forceinline__ Rec<SP::S> make_rec(const float* xq, long long t) {
+  Rec<SP::S> r;
+  if constexpr (SP::S == 3) {
+    r.a = make_float4(xq[0], xq[1], xq[2], __uint_as_float(static_cast<unsigned>(t)));
+  } else {
+    r.a = make_float4(xq[0], xq[1], xq[2], xq[3]);
+    r.b = make_uint4(static_cast<unsigned>(t), 0u, 0u, 0u);
+  }
+  return r;
+}
+
+// Exclusive scan out[i] = in[0] + ... + in[i - 1], i < n, by a 1024-thread
+// workgroup (in == out allowed); tmp: 16 words of LDS.  Each thread takes a
+// contiguous run of ceil(n / 1024) entries.
+__device__ __forceinline__ void block_scan_1024(const unsigned* in, unsigned* out, unsigned n, unsigned* tmp) {
+  const unsigned tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+  const unsigned per = (n + 1023u) >> 10;
+  const unsigned b = min(tid * per, n), e = min(b + per, n);
+  unsigned s = 0u;
+  for (unsigned i = b; i < e; ++i) s += in[i];
+  unsigned v = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned u = __shfl_up(v, off, 64);
+    if (lane >= static_cast<unsigned>(off)) v += u;
+  }
+  if (lane == 63u) tmp[wave] = v;
+  __syncthreads();
+  if (tid < 64u) {
+    unsigned w = tid < 16u ? tmp[tid] : 0u;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const unsigned u = __shfl_up(w, off, 64);
+      if (lane >= static_cast<unsigned>(off)) w += u;
+    }
+    if (tid < 16u) tmp[tid] = w;
+  }
+  __syncthreads();
+  unsigned run = v - s + (wave ? tmp[wave - 1] : 0u);
+  for (unsigned i = b; i < e; ++i) {
+    const unsigned c = in[i];
+    out[i] = run;
+    run += c;
+  }
+}
+
+// the whole exclusive scan of the key totals in one workgroup (small key counts)
+template <int = 0>
+__global__ void __launch_bounds__(1024) k_scan_single(const unsigned* __restrict__ in, unsigned* __restrict__ out,
+                                                      unsigned n) {
+  __shared__ unsigned tmp[16];
+  block_scan_1024(in, out, n, tmp);
+}
+
+// 3'. place records through an LDS counting sort of windows of W = 16384
+// items, so that a window's records of one key are written by neighbouring
+// lanes as one contiguous run.  Scattered single records cost about one
+// memory-fabric write request each; runs of several records share them.
+// Each thread keeps its 16 items' coordinates in registers (x is read once,
+// coalesced); after the window's key counts are scanned the records pass
+// through LDS in chunks of C = 2^cshift sorted positions.  LDS: the chunk's
+// records (item word = key << 15 | index in window), the tile's cursor per
+// key, and the window's key counts (then starts).  Keys < 2^17.
+template <class SP, bool SPLIT>
+__global__ void __launch_bounds__(1024) k_bin_place_win(Vol vol, BinGeom g, const float* __restrict__ x,
+                                                        const unsigned* __restrict__ hist,
+                                                        const unsigned* __restrict__ start,
+                                                        Rec<SP::S>* __restrict__ recs, int cshift) {
+  extern __shared__ unsigned lds_place[];
+  constexpr int R = 16;                 // items per thread and window
+  constexpr unsigned W = 1024u * R;
+  constexpr int U = kBinBatch;
+  const unsigned nk = g.nkeys, C = 1u << cshift, tid = threadIdx.x;
+  Rec<SP::S>* crec = reinterpret_cast<Rec<SP::S>*>(lds_place);   // C; its first 16 words also serve the scan
+  unsigned* gcur = reinterpret_cast<unsigned*>(crec + C);         // nk: next record slot of each key
+  unsigned* wst = gcur + nk;                                       // nk: window counts, then starts
+  const unsigned* h = hist + static_cast<size_t>(blockIdx.x) * nk;
+  for (unsigned i = tid; i < nk; i += blockDim.x) {
+    gcur[i] = h[i] + start[i];
+    wst[i] = 0u;
+  }
+  __syncthreads();
+  const long long t0 = static_cast<long long>(blockIdx.x) * g.tile_items;
+  const long long t1 = t0 + g.tile_items < g.items ? t0 + g.tile_items : g.items;
+  for (long long w0 = t0; w0 < t1; w0 += W) {
+    const unsigned nw = static_cast<unsigned>(t1 - w0 < static_cast<long long>(W) ? t1 - w0 : W);
+    float xr[R][SP::S];
+    unsigned pk[R];                     // key << 15 | rank of the item among the window's items of its key
+#pragma unroll
+    for (int r0 = 0; r0 < R; r0 += U) {
+      if (static_cast<unsigned>(r0) * 1024u >= nw) break;
+      int kk[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const unsigned j = static_cast<unsigned>(r0 + u) * 1024u + tid;
+        long long q;
+        split_item<SP, SPLIT>(w0 + (j < nw ? j : 0u), q, kk[u]);
+        load_x<SP>(x, q, xr[r0 + u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const unsigned j = static_cast<unsigned>(r0 + u) * 1024u + tid;
+        pk[r0 + u] = 0u;
+        if (j < nw) {
+          const unsigned key = item_key<SP, SPLIT>(vol, g, xr[r0 + u], kk[u]);
+          pk[r0 + u] = (key << 15) | atomicAdd(wst + key, 1u);
+        }
+      }
+    }
+    __syncthreads();
+    block_scan_1024(wst, wst, nk, reinterpret_cast<unsigned*>(crec));
+    __syncthreads();
+    for (unsigned c0 = 0; c0 < nw; c0 += C) {
+      // the records of sorted positions [c0, c0 + C) into LDS
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (static_cast<unsigned>(r) * 1024u >= nw) break;
+        const unsigned j = static_cast<unsigned>(r) * 1024u + tid;
+        if (j < nw) {
+          const unsigned key = pk[r] >> 15;
+          const unsigned sp = wst[key] + (pk[r] & 0x7fffu) - c0;
+          if (sp < C) crec[sp] = make_rec<SP>(xr[r], (key << 15) | j);
+        }
+      }
+      __syncthreads();
+      // lane i writes the i-th record of the chunk
+      const unsigned m = nw - c0 < C ? nw - c0 : C;
+      for (unsigned i = tid; i < m; i += blockDim.x) {
+        Rec<SP::S> rc = crec[i];
+        unsigned p;
+        if constexpr (SP::S == 3) p = __float_as_uint(rc.a.w); else p = rc.b.x;
+        const unsigned key = p >> 15;
+        const unsigned pos = gcur[key] + (c0 + i - wst[key]);
+        const unsigned item = static_cast<unsigned>(w0) + (p & 0x7fffu);
+        if constexpr (SP::S == 3) rc.a.w = __uint_as_float(item); else rc.b.x = item;
+        recs[pos] = rc;
+      }
+      __syncthreads();
+    }
+    // advance the cursors by the window's counts, clear the counts
+    for (unsigned key = tid; key < nk; key += blockDim.x)
+      gcur[key] += (key + 1u < nk ? wst[key + 1u] : nw) - wst[key];
+    __syncthreads();
+    for (unsigned key = tid; key < nk; key += blockDim.x) wst[key] = 0u;
+    __syncthreads();
   }
 }
 

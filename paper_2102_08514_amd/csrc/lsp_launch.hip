@@ -24,6 +24,7 @@ constexpr size_t kLdsEval = 64 * 1024;    // keep several evaluation workgroups 
 constexpr int kAbsMaxParts = 1024;         // blocks of the max |g| reduction
 constexpr unsigned long long kMinUnits = 1024;        // fewer units than this: smaller bricks
 constexpr unsigned long long kMinEvalGroups = 2048;   // fewer units than this: several workgroups per unit
+constexpr unsigned kScanSingle = 1u << 15;  // key totals scanned by one workgroup up to this count
 // key histogram budget: 3-D bricks stay at 16^3 cells for the big volumes
 // (fewer, fuller bricks amortise the staged halo); 4-D needs the full LDS to
 // keep 8^4 bricks with sub-region keys
@@ -116,6 +117,27 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
   return bn;
 }
 
+// Record placement through LDS windows of 16384 items (k_bin_place_win),
+// when a window holds two or more records per key on average, with chunks of
+// 2^cshift records passing through LDS; 0: the direct placement.  LDS: two
+// words per key and one record per chunk position.
+template <class SP>
+size_t place_window_lds(const BinGeom& g, int cshift) {
+  return 8ull * g.nkeys + (sizeof(Rec<SP::S>) << cshift);
+}
+
+template <class SP>
+int place_window_shift(const BinGeom& g) {
+  constexpr long long kWindow = 16384;
+  // 4-D items keep 64 coordinates per thread in registers and spill: direct placement
+  if (SP::S != 3 || g.nkeys >= (1u << 17)) return 0;
+  if (std::min<long long>(kWindow, g.tile_items) < 2ll * g.nkeys) return 0;
+  int c = 0;
+  for (int k = 10; k <= 14; ++k)
+    if (place_window_lds<SP>(g, k) <= kLdsMax) c = k;
+  return c;
+}
+
 template <class SP>
 lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
   const Bin bn = make_bin<SP>(v, n);
@@ -132,11 +154,22 @@ lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws,
   hipLaunchKernelGGL(k_bin_colscan<>, dim3(grid_of(g.nkeys + 1)), dim3(256), 0, st, hist, g.tiles, g.nkeys, tot);
   const unsigned nscan = g.nkeys + 1;
   const unsigned nblocks = (nscan + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_scan_blocks<>, dim3(nblocks), dim3(256), 0, st, tot, start, partial, nscan);
-  hipLaunchKernelGGL(k_scan_top<>, dim3(1), dim3(256), 0, st, partial, nblocks);
-  hipLaunchKernelGGL(k_scan_add<>, dim3(nblocks), dim3(256), 0, st, start, partial, nscan);
-  hipLaunchKernelGGL((k_bin_place<SP, SPLIT>), dim3(g.tiles), dim3(1024), lds, st, v->vol, g, x, hist, start,
-                     recs);
+  if (nscan <= kScanSingle) {
+    hipLaunchKernelGGL(k_scan_single<>, dim3(1), dim3(1024), 0, st, tot, start, nscan);
+  } else {
+    hipLaunchKernelGGL(k_scan_blocks<>, dim3(nblocks), dim3(256), 0, st, tot, start, partial, nscan);
+    hipLaunchKernelGGL(k_scan_top<>, dim3(1), dim3(256), 0, st, partial, nblocks);
+    hipLaunchKernelGGL(k_scan_add<>, dim3(nblocks), dim3(256), 0, st, start, partial, nscan);
+  }
+  const int cshift = place_window_shift<SP>(g);
+  if constexpr (SP::S == 3) {
+    if (cshift)
+      hipLaunchKernelGGL((k_bin_place_win<SP, SPLIT>), dim3(g.tiles), dim3(1024), place_window_lds<SP>(g, cshift),
+                         st, v->vol, g, x, hist, start, recs, cshift);
+  }
+  if (!cshift)
+    hipLaunchKernelGGL((k_bin_place<SP, SPLIT>), dim3(g.tiles), dim3(1024), lds, st, v->vol, g, x, hist, start,
+                       recs);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
 }
 
