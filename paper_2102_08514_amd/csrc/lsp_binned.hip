@@ -44,7 +44,8 @@ struct BinGeom {
   int upb;              // units per brick: M for coset-split items, else 1
   unsigned nunits;      // nbricks * upb
   int kpb;              // keys per unit: K for coset-split items, else 1
-  unsigned nkeys;       // nunits * kpb
+  unsigned okey;        // nunits * kpb: the outlier key (queries outside the brick grid)
+  unsigned nkeys;       // okey + 1
   int tiles;            // histogram tiles
   long long tile_items;
   long long n;          // queries
@@ -105,16 +106,22 @@ __device__ __forceinline__ int cell_of(const float* xq, int k, int d) {
   return (fl == fl) ? static_cast<int>(fl) : 0;
 }
 
+// An item's key: its unit and sub-region, or the outlier key when its cell
+// lies outside the brick grid.  Inside it, the item's stencil (every coset's,
+// for a whole query) lies in the unit's staged region, so the unit kernels
+// need no global-memory path.
 template <class SP, bool SPLIT>
 __device__ __forceinline__ unsigned item_key(const Vol& vol, const BinGeom& g, const float* xq, int k) {
   unsigned brick = 0, mul = 1;
+  bool inside = true;
 #pragma unroll
   for (int d = 0; d < SP::S; ++d) {
-    int b = cell_of<SP>(xq, k, d) >> g.bshift;
-    b = b < 0 ? 0 : (b >= g.nb[d] ? g.nb[d] - 1 : b);
+    const int b = cell_of<SP>(xq, k, d) >> g.bshift;
+    inside = inside && b >= 0 && b < g.nb[d];
     brick += static_cast<unsigned>(b) * mul;
     mul *= static_cast<unsigned>(g.nb[d]);
   }
+  if (!inside) return g.okey;
   const unsigned unit = brick * static_cast<unsigned>(g.upb) + (SPLIT ? static_cast<unsigned>(k) : 0u);
   unsigned key = unit * static_cast<unsigned>(g.kpb);
   if constexpr (SPLIT) {
@@ -638,12 +645,17 @@ __device__ __forceinline__ void coset_binned_folded(const Vol& vol, const StageI
                                                     int k, const Folded<SP, AT>& F, AT& f, AT* gx) {
   const int ob = SP::template orbit<AT>(F.up);
   AT b[SP::NMON];
-  bool staged = false;
-  if constexpr (STAGE) staged = stageable<SP, AT>(si, F);
-  if (staged) {
-    GatherLds<SP, AT> g;
-    g.init(region, si, F);
-    SP::template b_any<AT>(ob, g, b);
+  if constexpr (STAGE) {
+    // every item of a unit is stageable (queries outside the brick grid are
+    // scheduled apart, under the outlier key); a violation shows as NaN
+    if (stageable<SP, AT>(si, F)) {
+      GatherLds<SP, AT> g;
+      g.init(region, si, F);
+      SP::template b_any<AT>(ob, g, b);
+    } else {
+#pragma unroll
+      for (int m = 0; m < SP::NMON; ++m) b[m] = AT(__builtin_nanf(""));
+    }
   } else if (F.interior) {
     Gather<SP, CT, AT, false> g;
     g.init(vol, k, F);
@@ -691,10 +703,64 @@ __device__ __forceinline__ bool unit_range(const BinGeom& g, const unsigned* sta
   return u.lo != u.hi;
 }
 
-// 4a. forward, one workgroup per unit.
+// One work item of the binned forward: record coordinates xf and item id,
+// target yq (MSE) and schedule position t.
 //   not SPLIT: f[q] (and grad[q]) directly.  SPLIT: fpart[k * n + q] (and
 //   gpart) for the combine kernel.  MSE (not SPLIT): also dL/df, and grad
 //   receives dL/dx = dL/df * grad f.
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE>
+__device__ __forceinline__ void eval_item(const Vol& vol, const BinGeom& g, const StageInfo<SP, AT>& si,
+                                          const AT* lds, const float* xf, unsigned item, float yq, unsigned t,
+                                          AT* __restrict__ f, AT* __restrict__ grad, float inv_n,
+                                          float* __restrict__ dldf, float* __restrict__ gsave, float& r2) {
+  long long q;
+  int k;
+  split_item<SP, SPLIT>(item, q, k);
+  AT xq[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) xq[d] = static_cast<AT>(xf[d]);
+  AT acc = AT(0);
+  AT gx[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) gx[d] = AT(0);
+  if constexpr (SPLIT) {
+    coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds, k, xq, acc, gx);
+    const long long slot = static_cast<long long>(k) * g.n + q;
+    f[slot] = acc;
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) grad[slot * SP::S + d] = gx[d];
+    }
+  } else {
+    if constexpr (complement_coset<SP>()) {
+      Folded<SP, AT> F0, F1;
+      fold_query<SP, AT>(xq, 0, vol, F0);
+      coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, lds, 0, F0, acc, gx);
+      fold_complement<SP, AT>(F0, vol, F1);
+      coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, STAGE ? lds + si.vol : lds, 1, F1, acc, gx);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < SP::M; ++kk)
+        coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, STAGE ? lds + kk * si.vol : lds, kk, xq, acc, gx);
+    }
+    if (f) f[q] = acc;    // optional for the MSE head
+    AT scale = AT(1);
+    if constexpr (MSE) {
+      const float r = static_cast<float>(acc) - yq;
+      const float dl = 2.f * r * inv_n;
+      if (dldf) dldf[q] = dl;
+      if (gsave) gsave[t] = dl;   // in schedule order, for the fused backward
+      r2 += r * r;
+      scale = static_cast<AT>(dl);
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = scale * gx[d];
+    }
+  }
+}
+
+// 4a. forward, one workgroup per unit (see eval_item for the outputs)
 template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE, int NT>
 __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
                                                      const unsigned* __restrict__ start, AT* __restrict__ f,
@@ -728,51 +794,30 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
     const float yq = ycur;
     cur = nxt;
     ycur = ynxt;
-    long long q;
-    int k;
-    split_item<SP, SPLIT>(item, q, k);
-    AT xq[SP::S];
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) xq[d] = static_cast<AT>(xf[d]);
-    AT acc = AT(0);
-    AT gx[SP::S];
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) gx[d] = AT(0);
-    if constexpr (SPLIT) {
-      coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds, k, xq, acc, gx);
-      const long long slot = static_cast<long long>(k) * g.n + q;
-      f[slot] = acc;
-      if constexpr (GRAD) {
-#pragma unroll
-        for (int d = 0; d < SP::S; ++d) grad[slot * SP::S + d] = gx[d];
-      }
-    } else {
-      if constexpr (complement_coset<SP>()) {
-        Folded<SP, AT> F0, F1;
-        fold_query<SP, AT>(xq, 0, vol, F0);
-        coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, lds, 0, F0, acc, gx);
-        fold_complement<SP, AT>(F0, vol, F1);
-        coset_binned_folded<SP, CT, AT, GRAD, STAGE>(vol, si, lds + si.vol, 1, F1, acc, gx);
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < SP::M; ++kk)
-          coset_binned<SP, CT, AT, GRAD, STAGE>(vol, si, lds + kk * si.vol, kk, xq, acc, gx);
-      }
-      if (f) f[q] = acc;    // optional for the MSE head
-      AT scale = AT(1);
-      if constexpr (MSE) {
-        const float r = static_cast<float>(acc) - yq;
-        const float dl = 2.f * r * inv_n;
-        if (dldf) dldf[q] = dl;
-        if (gsave) gsave[t] = dl;   // in schedule order, for the fused backward
-        r2 += r * r;
-        scale = static_cast<AT>(dl);
-      }
-      if constexpr (GRAD) {
-#pragma unroll
-        for (int d = 0; d < SP::S; ++d) grad[q * SP::S + d] = scale * gx[d];
-      }
-    }
+    eval_item<SP, CT, AT, GRAD, SPLIT, STAGE, MSE>(vol, g, si, lds, xf, item, yq, t, f, grad, inv_n, dldf, gsave, r2);
+  }
+  if constexpr (MSE && !SPLIT) mse_reduce(r2, static_cast<double>(inv_n), loss);
+}
+
+// 4a'. forward of the items under the outlier key (queries outside the brick
+// grid), from global memory with zero padding; a grid-stride loop over the
+// key's records, usually none
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool MSE>
+__global__ void __launch_bounds__(256) k_eval_outliers(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
+                                                       const unsigned* __restrict__ start, AT* __restrict__ f,
+                                                       AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
+                                                       float* __restrict__ dldf, double* __restrict__ loss,
+                                                       float* __restrict__ gsave) {
+  const unsigned lo = start[g.okey], hi = start[g.okey + 1];
+  StageInfo<SP, AT> si{};
+  float r2 = 0.f;
+  for (unsigned t = lo + blockIdx.x * blockDim.x + threadIdx.x; t < hi; t += gridDim.x * blockDim.x) {
+    float xf[SP::S];
+    const unsigned item = rec_item<SP>(recs[t], xf);
+    float yq = 0.f;
+    if constexpr (MSE && !SPLIT) yq = y[item];
+    eval_item<SP, CT, AT, GRAD, SPLIT, false, MSE>(vol, g, si, nullptr, xf, item, yq, t, f, grad, inv_n, dldf,
+                                                   gsave, r2);
   }
   if constexpr (MSE && !SPLIT) mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
@@ -813,11 +858,101 @@ __global__ void __launch_bounds__(256) k_combine(const AT* __restrict__ fpart, c
   if constexpr (MSE) mse_reduce(r2, static_cast<double>(inv_n), loss);
 }
 
+// One work item of the binned adjoint: grad_c += g w(x) and, with GRADX,
+// grad_x = g grad f (SPLIT: the (query, coset) partial).  LDS_G: the
+// scatter-add goes into the unit's fixed-point LDS region; returns false if
+// the item's stencil leaves that region (never, for items of a unit).  Else
+// (items under the outlier key) it goes to global memory with float atomics.
+template <class SP, class CT, bool GRADX, bool SPLIT, bool LDS_G, bool STAGE_C>
+__device__ __forceinline__ bool adjoint_item(const Vol& vol, const GradVol& gvol, const BinGeom& g,
+                                             const StageInfo<SP, float>& si, unsigned long long* lds_g,
+                                             const float* lds_c, int shift, const float* xq, unsigned item, float gq,
+                                             float* __restrict__ grad_x) {
+  constexpr int NC = SPLIT ? 1 : SP::M;
+  long long q;
+  int k;
+  split_item<SP, SPLIT>(item, q, k);
+  // a query that is not finite adds nothing (fixed point cannot carry NaN);
+  // its grad_x is NaN
+  bool finite = true;
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) finite = finite && isfinite(xq[d]);
+  if (!finite) {
+    if constexpr (GRADX) {
+      const long long slot = SPLIT ? static_cast<long long>(k) * g.n + q : q;
+#pragma unroll
+      for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = __int_as_float(0x7fc00000);
+    }
+    return true;
+  }
+  bool ok = true;
+  float gx[SP::S];
+#pragma unroll
+  for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
+#pragma unroll
+  for (int kk = 0; kk < NC; ++kk) {
+    const int kc = SPLIT ? k : kk;
+    Folded<SP, float> F;
+    fold_query<SP, float>(xq, kc, vol, F);
+    const int ob = SP::template orbit<float>(F.up);
+    float mono[SP::NMON];
+    monomials<SP, float>(F.up, ob, mono);
+    bool staged = false;
+    if constexpr (LDS_G) {
+      staged = stageable<SP, float>(si, F);
+      if (staged) {
+        ScatterLds<SP> sc;
+        sc.init(lds_g + kk * si.vol, si, F, ldexpf(gq, shift));
+        SP::template w_any<float>(ob, sc, mono);
+      } else {
+        ok = false;
+      }
+    } else if (F.interior) {
+      Scatter<SP, false> sc;
+      sc.init(vol, pick<SP::M>(gvol.base, kc), F, gq);
+      SP::template w_any<float>(ob, sc, mono);
+    } else {
+      Scatter<SP, true> sc;
+      sc.init(vol, pick<SP::M>(gvol.base, kc), F, gq);
+      SP::template w_any<float>(ob, sc, mono);
+    }
+    if constexpr (GRADX) {
+      float b[SP::NMON];
+      if constexpr (STAGE_C) {
+        if (staged) {
+          GatherLds<SP, float> gg;
+          gg.init(lds_c + kk * si.vol, si, F);
+          SP::template b_any<float>(ob, gg, b);
+        } else {
+#pragma unroll
+          for (int m = 0; m < SP::NMON; ++m) b[m] = __builtin_nanf("");
+        }
+      } else if (F.interior) {
+        Gather<SP, CT, float, false> gg;
+        gg.init(vol, kc, F);
+        SP::template b_any<float>(ob, gg, b);
+      } else {
+        Gather<SP, CT, float, true> gg;
+        gg.init(vol, kc, F);
+        SP::template b_any<float>(ob, gg, b);
+      }
+      float dpsi[SP::S];
+      (void)poly_eval<SP, float, true>(b, mono, dpsi);
+      unfold_grad<SP, float>(F, dpsi, gx);
+    }
+  }
+  if constexpr (GRADX) {
+    const long long slot = SPLIT ? static_cast<long long>(k) * g.n + q : q;
+#pragma unroll
+    for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = gq * gx[d];
+  }
+  return ok;
+}
+
 // 5a. adjoint, one workgroup per unit: scatter-add g * w into an LDS copy of
 // the unit's region, then store the region to the unit's private slot
 // priv[unit][ncos][vol] with plain writes (k_adjoint_gather sums the slots).
-// Items whose stencil leaves the region (queries outside the volume, clamped
-// to an edge brick) scatter with global atomics instead.
+// Queries outside the brick grid are not in any unit (k_adjoint_outliers).
 //   GRADX, not SPLIT: grad_x[q] = g_q * grad f; SPLIT: gpart[k * n + q].
 template <class SP, class CT, bool GRADX, bool SPLIT, bool STAGE_C>
 __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, BinGeom g,
@@ -847,88 +982,50 @@ __global__ void __launch_bounds__(512) k_adjoint_binned(Vol vol, GradVol gvol, B
   Rec<SP::S> cur = recs[min(u.lo + threadIdx.x, last)];
   Rec<SP::S> nxt = recs[min(u.lo + threadIdx.x + blockDim.x, last)];
   float gcur = g_sorted ? gout[min(u.lo + threadIdx.x, last)] : gout[rec_query<SP, SPLIT>(cur)];
+  int bad = 0;
   for (unsigned t = u.lo + threadIdx.x; t < u.hi; t += blockDim.x) {
     const Rec<SP::S> nn = recs[min(t + 2 * blockDim.x, last)];
     const float gnxt = g_sorted ? gout[min(t + blockDim.x, last)] : gout[rec_query<SP, SPLIT>(nxt)];
     float xq[SP::S];
     const unsigned item = rec_item<SP>(cur, xq);
-    long long q;
-    int k;
-    split_item<SP, SPLIT>(item, q, k);
     const float gq = gcur;
     cur = nxt;
     nxt = nn;
     gcur = gnxt;
-    // a query that is not finite adds nothing (fixed point cannot carry NaN);
-    // its grad_x is NaN
-    bool finite = true;
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) finite = finite && isfinite(xq[d]);
-    if (!finite) {
-      if constexpr (GRADX) {
-        const long long slot = SPLIT ? static_cast<long long>(k) * g.n + q : q;
-#pragma unroll
-        for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = __int_as_float(0x7fc00000);
-      }
-      continue;
-    }
-    float gx[SP::S];
-#pragma unroll
-    for (int d = 0; d < SP::S; ++d) gx[d] = 0.f;
-#pragma unroll
-    for (int kk = 0; kk < NC; ++kk) {
-      const int kc = SPLIT ? k : kk;
-      Folded<SP, float> F;
-      fold_query<SP, float>(xq, kc, vol, F);
-      const int ob = SP::template orbit<float>(F.up);
-      float mono[SP::NMON];
-      monomials<SP, float>(F.up, ob, mono);
-      const bool staged = stageable<SP, float>(si, F);
-      if (staged) {
-        ScatterLds<SP> sc;
-        sc.init(lds_g + kk * si.vol, si, F, ldexpf(gq, shift));
-        SP::template w_any<float>(ob, sc, mono);
-      } else if (F.interior) {
-        Scatter<SP, false> sc;
-        sc.init(vol, pick<SP::M>(gvol.base, kc), F, gq);
-        SP::template w_any<float>(ob, sc, mono);
-      } else {
-        Scatter<SP, true> sc;
-        sc.init(vol, pick<SP::M>(gvol.base, kc), F, gq);
-        SP::template w_any<float>(ob, sc, mono);
-      }
-      if constexpr (GRADX) {
-        float b[SP::NMON];
-        if (STAGE_C && staged) {
-          GatherLds<SP, float> gg;
-          gg.init(lds_c + kk * si.vol, si, F);
-          SP::template b_any<float>(ob, gg, b);
-        } else if (F.interior) {
-          Gather<SP, CT, float, false> gg;
-          gg.init(vol, kc, F);
-          SP::template b_any<float>(ob, gg, b);
-        } else {
-          Gather<SP, CT, float, true> gg;
-          gg.init(vol, kc, F);
-          SP::template b_any<float>(ob, gg, b);
-        }
-        float dpsi[SP::S];
-        (void)poly_eval<SP, float, true>(b, mono, dpsi);
-        unfold_grad<SP, float>(F, dpsi, gx);
-      }
-    }
-    if constexpr (GRADX) {
-      const long long slot = SPLIT ? static_cast<long long>(k) * g.n + q : q;
-#pragma unroll
-      for (int d = 0; d < SP::S; ++d) grad_x[slot * SP::S + d] = gq * gx[d];
-    }
+    if (!adjoint_item<SP, CT, GRADX, SPLIT, true, STAGE_C>(vol, gvol, g, si, lds_g, lds_c, shift, xq, item, gq,
+                                                           grad_x))
+      bad = 1;
   }
-  __syncthreads();
-  // back to float; a non-finite upstream gradient makes the region NaN
-  const bool finite = gmax <= 3.402823466e38f;
+  // back to float; a non-finite upstream gradient makes the region NaN (and
+  // so would an item outside the region, which the schedule never places in
+  // a unit)
+  const bool finite = gmax <= 3.402823466e38f && !__syncthreads_or(bad);
   float* out = priv + static_cast<size_t>(u.unit) * NC * si.vol;
   for (int e = threadIdx.x; e < NC * si.vol; e += blockDim.x)
     out[e] = finite ? ldexpf(static_cast<float>(static_cast<long long>(lds_g[e])), -shift) : __int_as_float(0x7fc00000);
+}
+
+// 5a'. adjoint of the items under the outlier key (queries outside the brick
+// grid): float atomics into grad_c, before the gather pass adds the units'
+// regions; a grid-stride loop over the key's records, usually none
+template <class SP, class CT, bool GRADX, bool SPLIT>
+__global__ void __launch_bounds__(256) k_adjoint_outliers(Vol vol, GradVol gvol, BinGeom g,
+                                                          const Rec<SP::S>* __restrict__ recs,
+                                                          const unsigned* __restrict__ start,
+                                                          const float* __restrict__ gout, float* __restrict__ grad_x,
+                                                          int g_sorted) {
+  const unsigned lo = start[g.okey], hi = start[g.okey + 1];
+  StageInfo<SP, float> si{};
+  for (unsigned t = lo + blockIdx.x * blockDim.x + threadIdx.x; t < hi; t += gridDim.x * blockDim.x) {
+    float xq[SP::S];
+    const unsigned item = rec_item<SP>(recs[t], xq);
+    long long q;
+    int k;
+    split_item<SP, SPLIT>(item, q, k);
+    const float gq = g_sorted ? gout[t] : gout[q];
+    (void)adjoint_item<SP, CT, GRADX, SPLIT, false, false>(vol, gvol, g, si, nullptr, nullptr, 0, xq, item, gq,
+                                                           grad_x);
+  }
 }
 
 // max |g| over the upstream gradient, as the bits of a non-negative float

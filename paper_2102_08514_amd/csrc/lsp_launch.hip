@@ -25,6 +25,7 @@ constexpr int kAbsMaxParts = 1024;         // blocks of the max |g| reduction
 constexpr unsigned long long kMinUnits = 1024;        // fewer units than this: smaller bricks
 constexpr unsigned long long kMinEvalGroups = 2048;   // fewer units than this: several workgroups per unit
 constexpr unsigned kScanSingle = 1u << 15;  // key totals scanned by one workgroup up to this count
+constexpr unsigned kOutlierGroups = 128;      // workgroups of the outlier kernels (grid-stride loops)
 // key histogram budget: 3-D bricks stay at 16^3 cells for the big volumes
 // (fewer, fuller bricks amortise the staged halo); 4-D needs the full LDS to
 // keep 8^4 bricks with sub-region keys
@@ -68,17 +69,18 @@ Bin make_bin(const lsp_vol_s* v, int64_t n) {
       nbr *= static_cast<unsigned long long>((v->vol.dims[d] + (1 << bshift) - 1) >> bshift);
     return nbr;
   };
-  g.bshift = units_at(3) * g.upb < kMinUnits && units_at(2) * g.upb * g.kpb * 4 <= hist_budget<SP>() ? 2 : 3;
+  g.bshift = units_at(3) * g.upb < kMinUnits && (units_at(2) * g.upb * g.kpb + 1) * 4 <= hist_budget<SP>() ? 2 : 3;
   for (;; ++g.bshift) {
     unsigned long long nbr = 1;
     for (int d = 0; d < SP::S; ++d) {
       g.nb[d] = (v->vol.dims[d] + (1 << g.bshift) - 1) >> g.bshift;
       nbr *= static_cast<unsigned long long>(g.nb[d]);
     }
-    if (nbr * g.upb * g.kpb * 4 <= hist_budget<SP>()) {
+    if ((nbr * g.upb * g.kpb + 1) * 4 <= hist_budget<SP>()) {
       g.nbricks = static_cast<unsigned>(nbr);
       g.nunits = static_cast<unsigned>(nbr * g.upb);
-      g.nkeys = static_cast<unsigned>(nbr * g.upb * g.kpb);
+      g.okey = static_cast<unsigned>(nbr * g.upb * g.kpb);
+      g.nkeys = g.okey + 1;
       break;
     }
   }
@@ -189,9 +191,13 @@ lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT*
   const dim3 grid(unit_grid(g.nunits * g.wpu));
   // the unit's coefficients are staged in LDS when the region fits
   constexpr int NT = SP::S == 3 ? 256 : 512;
-#define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                                 \
-  hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT), bn.lds_eval, \
-                     st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave)
+#define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                                   \
+  do {                                                                                                           \
+    hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT), bn.lds_eval, \
+                       st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave);                          \
+    hipLaunchKernelGGL((k_eval_outliers<SP, CT, AT, GRAD_, SPLIT, MSE_>), dim3(kOutlierGroups), dim3(256), 0,    \
+                       st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave);                          \
+  } while (0)
   if constexpr (SPLIT) {
     AT* fo = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_fpart);
     AT* go = reinterpret_cast<AT*>(const_cast<char*>(base) + bn.off_gpart);
@@ -324,6 +330,13 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   const unsigned parts = std::min(grid_of(n), static_cast<unsigned>(kAbsMaxParts));
   hipLaunchKernelGGL(k_absmax_partial<>, dim3(parts), dim3(256), 0, st, g, static_cast<long long>(n), gparts);
   hipLaunchKernelGGL(k_absmax_final<>, dim3(1), dim3(1024), 0, st, gparts, static_cast<int>(parts), gmax);
+  // items outside the brick grid: float atomics into grad_c, before the gather pass
+  if (grad_x)
+    hipLaunchKernelGGL((k_adjoint_outliers<SP, CT, true, SPLIT>), dim3(kOutlierGroups), dim3(256), 0, st, v->vol, gv,
+                       gm, recs, start, g, gx_out, gsorted);
+  else
+    hipLaunchKernelGGL((k_adjoint_outliers<SP, CT, false, SPLIT>), dim3(kOutlierGroups), dim3(256), 0, st, v->vol,
+                       gv, gm, recs, start, g, gx_out, gsorted);
   if (grad_x) {
     if (bn.adj_stage_c)
       hipLaunchKernelGGL((k_adjoint_binned<SP, CT, true, SPLIT, true>), grid, dim3(512), bn.lds_adj, st, v->vol, gv,
