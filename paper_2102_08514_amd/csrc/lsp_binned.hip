@@ -1065,17 +1065,43 @@ __global__ void __launch_bounds__(1024) k_absmax_final(const unsigned* __restric
   if (threadIdx.x == 0) *out = m;
 }
 
+// n / d for any 32-bit n by a multiply-high (Granlund and Montgomery's
+// round-up method): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,
+// t = mulhi(m, n), n / d = (t + ((n - t) >> 1)) >> (l - 1); l = 0 means d = 1.
+struct UDiv {
+  unsigned m;
+  int l;
+};
+
+__host__ inline UDiv make_udiv(unsigned d) {
+  if (d <= 1u) return UDiv{0u, 0};
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  return UDiv{static_cast<unsigned>(((1ull << 32) * ((1ull << l) - d)) / d + 1ull), l};
+}
+
+__device__ __forceinline__ unsigned udiv(unsigned n, UDiv v) {
+  if (v.l == 0) return n;
+  const unsigned t = __umulhi(v.m, n);
+  return (t + ((n - t) >> 1)) >> (v.l - 1);
+}
+
+// divisors of the gather pass's index decomposition: the row length d0 (short
+// rows) and the extents of axes 1 .. S-1
+struct GatherDiv {
+  UDiv d0;
+  UDiv dim[kMaxDim];
+};
+
 // 5b. grad_c[k][site] += sum of the private regions of the units covering the
 // site.  blockIdx.y is the coset; a block covers a run of 256 sites along
 // axis 0 of one row of the other axes, or, for short rows (n_0 < 256), rpb
 // whole rows.  Every index is 32-bit.
-__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-
 template <class SP, bool SPLIT>
 __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, BinGeom g,
                                                         const unsigned* __restrict__ start,
                                                         const float* __restrict__ priv, unsigned segs,
-                                                        unsigned rpb, unsigned rows) {
+                                                        unsigned rpb, unsigned rows, GatherDiv gd) {
   constexpr int S = SP::S;
   constexpr int NC = SPLIT ? 1 : SP::M;
   constexpr int MG = Staged<SP>::MARGIN;
@@ -1083,7 +1109,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
   const unsigned d0 = static_cast<unsigned>(vol.dims[0]);
   const unsigned blk = blockIdx.x / segs;
   const unsigned seg = blockIdx.x - blk * segs;
-  const unsigned roff = rpb == 1 ? 0u : threadIdx.x / d0;
+  const unsigned roff = rpb == 1 ? 0u : udiv(threadIdx.x, gd.d0);
   int c[S];
   c[0] = static_cast<int>(rpb == 1 ? seg * 256u + threadIdx.x : threadIdx.x - roff * d0);
   const unsigned row = blk * rpb + roff;
@@ -1092,19 +1118,21 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
     unsigned r = row;
 #pragma unroll
     for (int d = 1; d < S; ++d) {
-      c[d] = static_cast<int>(r % static_cast<unsigned>(vol.dims[d]));
-      r /= static_cast<unsigned>(vol.dims[d]);
+      const unsigned qd = udiv(r, gd.dim[d]);
+      c[d] = static_cast<int>(r - qd * static_cast<unsigned>(vol.dims[d]));
+      r = qd;
     }
   }
-  const int B = 1 << g.bshift;
-  const int W = Staged<SP>::width(B);
-  const int vol_r = Staged<SP>::volume(B);
+  const int bs = g.bshift;
+  const int W = Staged<SP>::width(1 << bs);
+  const int vol_r = Staged<SP>::volume(1 << bs);
   // bricks b whose region [b B - MARGIN + OMIN, b B + B - 1 + OMAX] holds c
+  // (arithmetic shifts floor negative values)
   int blo[S], bcnt[S];
 #pragma unroll
   for (int d = 0; d < S; ++d) {
-    int lo = floor_div(c[d] - (B - 1 + SP::OMAX) + B - 1, B);
-    int hi = floor_div(c[d] + MG - SP::OMIN, B);
+    int lo = (c[d] - SP::OMAX) >> bs;
+    int hi = (c[d] + MG - SP::OMIN) >> bs;
     lo = lo < 0 ? 0 : lo;
     hi = hi >= g.nb[d] ? g.nb[d] - 1 : hi;
     blo[d] = lo;
@@ -1124,7 +1152,7 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
             const int b = blo[d] + idx[d];
             brick += static_cast<unsigned>(b) * mul;
             mul *= static_cast<unsigned>(g.nb[d]);
-            local += (c[d] - (b * B - MG + SP::OMIN)) * ls;
+            local += (c[d] - (b << bs) + MG - SP::OMIN) * ls;
             ls *= W;
           }
           const unsigned unit = brick * g.upb + (SPLIT ? static_cast<unsigned>(k) : 0u);

@@ -350,8 +350,11 @@ lsp_status launch_adj(const lsp_vol_s* v, const float* x, const float* g, int64_
   }
   const unsigned rpb = v->vol.dims[0] >= 256 ? 1u : 256u / static_cast<unsigned>(v->vol.dims[0]);
   const unsigned blocks = static_cast<unsigned>((rows + rpb - 1) / rpb) * segs;
+  GatherDiv gd{};
+  gd.d0 = make_udiv(static_cast<unsigned>(v->vol.dims[0]));
+  for (int d = 1; d < SP::S; ++d) gd.dim[d] = make_udiv(static_cast<unsigned>(v->vol.dims[d]));
   hipLaunchKernelGGL((k_adjoint_gather<SP, SPLIT>), dim3(blocks, SP::M), dim3(256), 0, st, v->vol, gv, gm, start, priv,
-                     segs, rpb, static_cast<unsigned>(rows));
+                     segs, rpb, static_cast<unsigned>(rows), gd);
   if (SPLIT && grad_x)
     hipLaunchKernelGGL((k_combine_gx<SP>), dim3(fill_grid(n * SP::S)), dim3(256), 0, st, gx_out,
                        static_cast<long long>(n), grad_x);
