@@ -761,12 +761,13 @@ __device__ __forceinline__ void eval_item(const Vol& vol, const BinGeom& g, cons
 }
 
 // 4a. forward, one workgroup per unit (see eval_item for the outputs)
-template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE, int NT>
-__global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
-                                                     const unsigned* __restrict__ start, AT* __restrict__ f,
-                                                     AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
-                                                     float* __restrict__ dldf, double* __restrict__ loss,
-                                                     float* __restrict__ gsave) {
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE>
+__device__ __forceinline__ void eval_binned_body(const Vol& vol, const BinGeom& g,
+                                                 const Rec<SP::S>* __restrict__ recs,
+                                                 const unsigned* __restrict__ start, AT* __restrict__ f,
+                                                 AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
+                                                 float* __restrict__ dldf, double* __restrict__ loss,
+                                                 float* __restrict__ gsave) {
   extern __shared__ unsigned char smem[];
   AT* lds = reinterpret_cast<AT*>(smem);
   UnitRange u;
@@ -797,6 +798,26 @@ __global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Re
     eval_item<SP, CT, AT, GRAD, SPLIT, STAGE, MSE>(vol, g, si, lds, xf, item, yq, t, f, grad, inv_n, dldf, gsave, r2);
   }
   if constexpr (MSE && !SPLIT) mse_reduce(r2, static_cast<double>(inv_n), loss);
+}
+
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE, int NT>
+__global__ void __launch_bounds__(NT) k_eval_binned(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs,
+                                                     const unsigned* __restrict__ start, AT* __restrict__ f,
+                                                     AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
+                                                     float* __restrict__ dldf, double* __restrict__ loss,
+                                                     float* __restrict__ gsave) {
+  eval_binned_body<SP, CT, AT, GRAD, SPLIT, STAGE, MSE>(vol, g, recs, start, f, grad, y, inv_n, dldf, loss, gsave);
+}
+
+// The same for 4-D units (512 threads) held to 128 VGPRs, i.e. 4 waves per
+// SIMD and two workgroups per CU, where the unconstrained code needs a few
+// registers more.
+template <class SP, class CT, class AT, bool GRAD, bool SPLIT, bool STAGE, bool MSE, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_eval_binned_w4(Vol vol, BinGeom g, const Rec<SP::S>* __restrict__ recs, const unsigned* __restrict__ start,
+                 AT* __restrict__ f, AT* __restrict__ grad, const float* __restrict__ y, float inv_n,
+                 float* __restrict__ dldf, double* __restrict__ loss, float* __restrict__ gsave) {
+  eval_binned_body<SP, CT, AT, GRAD, SPLIT, STAGE, MSE>(vol, g, recs, start, f, grad, y, inv_n, dldf, loss, gsave);
 }
 
 // 4a'. forward of the items under the outlier key (queries outside the brick

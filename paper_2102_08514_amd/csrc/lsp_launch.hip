@@ -193,8 +193,12 @@ lsp_status launch_binned_eval(const lsp_vol_s* v, int64_t n, const void* ws, AT*
   constexpr int NT = SP::S == 3 ? 256 : 512;
 #define LSP_EVAL_BINNED(GRAD_, STAGE_, MSE_)                                                                   \
   do {                                                                                                           \
-    hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT), bn.lds_eval, \
-                       st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave);                          \
+    if constexpr (SP::S == 4)                                                                                    \
+      hipLaunchKernelGGL((k_eval_binned_w4<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT),          \
+                         bn.lds_eval, st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave);          \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_eval_binned<SP, CT, AT, GRAD_, SPLIT, STAGE_, MSE_, NT>), grid, dim3(NT),             \
+                         bn.lds_eval, st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave);          \
     hipLaunchKernelGGL((k_eval_outliers<SP, CT, AT, GRAD_, SPLIT, MSE_>), dim3(kOutlierGroups), dim3(256), 0,    \
                        st, v->vol, g, recs, start, fo, go, y, inv_n, dldf, loss, gsave);                          \
   } while (0)
