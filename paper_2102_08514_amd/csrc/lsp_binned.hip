@@ -393,6 +393,85 @@ __global__ void __launch_bounds__(1024) k_bin_place_win(Vol vol, BinGeom g, cons
   }
 }
 
+// 3''. the windowed placement for (query, coset) items of splines with many
+// cosets (M >= 4): a window of 16384 items covers at most 16384 / M + 1
+// queries, whose coordinates are kept in LDS (one copy per query instead of
+// one per item in registers), and the window's items in key order are kept
+// as packed words key << 15 | index in window, so each key's records of a
+// window leave as one contiguous run.  LDS: the window's queries, the sorted
+// words, the tile's cursor per key and the window's key counts (then
+// starts).  Keys < 2^17.
+template <class SP>
+__global__ void __launch_bounds__(1024) k_bin_place_winq(Vol vol, BinGeom g, const float* __restrict__ x,
+                                                         const unsigned* __restrict__ hist,
+                                                         const unsigned* __restrict__ start,
+                                                         Rec<SP::S>* __restrict__ recs) {
+  extern __shared__ unsigned lds_place[];
+  constexpr int S = SP::S, M = SP::M, R = 16;
+  constexpr unsigned W = 1024u * R;
+  constexpr unsigned WQ = W / M + 2;    // queries a window can touch
+  const unsigned nk = g.nkeys, tid = threadIdx.x;
+  float* xw = reinterpret_cast<float*>(lds_place);                 // WQ * S
+  unsigned* sorted = lds_place + WQ * S;                            // W; its first 16 words also serve the scan
+  unsigned* gcur = sorted + W;                                      // nk
+  unsigned* wst = gcur + nk;                                        // nk
+  const unsigned* h = hist + static_cast<size_t>(blockIdx.x) * nk;
+  for (unsigned i = tid; i < nk; i += blockDim.x) {
+    gcur[i] = h[i] + start[i];
+    wst[i] = 0u;
+  }
+  __syncthreads();
+  const long long t0 = static_cast<long long>(blockIdx.x) * g.tile_items;
+  const long long t1 = t0 + g.tile_items < g.items ? t0 + g.tile_items : g.items;
+  for (long long w0 = t0; w0 < t1; w0 += W) {
+    const unsigned nw = static_cast<unsigned>(t1 - w0 < static_cast<long long>(W) ? t1 - w0 : W);
+    const long long q0 = w0 / M;
+    const unsigned nq = static_cast<unsigned>((w0 + nw - 1) / M - q0 + 1);
+    // the window's queries into LDS, coalesced
+    for (unsigned e = tid; e < nq * S; e += blockDim.x) xw[e] = x[q0 * S + e];
+    __syncthreads();
+    unsigned pk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const unsigned j = static_cast<unsigned>(r) * 1024u + tid;
+      pk[r] = 0u;
+      if (j < nw) {
+        long long q;
+        int k;
+        split_item<SP, true>(w0 + j, q, k);
+        const unsigned key = item_key<SP, true>(vol, g, xw + (q - q0) * S, k);
+        pk[r] = (key << 15) | atomicAdd(wst + key, 1u);
+      }
+    }
+    __syncthreads();
+    block_scan_1024(wst, wst, nk, sorted);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const unsigned j = static_cast<unsigned>(r) * 1024u + tid;
+      if (j < nw) {
+        const unsigned key = pk[r] >> 15;
+        sorted[wst[key] + (pk[r] & 0x7fffu)] = (key << 15) | j;
+      }
+    }
+    __syncthreads();
+    // lane i writes the i-th record of the window
+    for (unsigned i = tid; i < nw; i += blockDim.x) {
+      const unsigned p = sorted[i];
+      const unsigned key = p >> 15;
+      const long long t = w0 + (p & 0x7fffu);
+      const float* xq = xw + (t / M - q0) * S;
+      recs[gcur[key] + (i - wst[key])] = make_rec<SP>(xq, t);
+    }
+    __syncthreads();
+    for (unsigned key = tid; key < nk; key += blockDim.x)
+      gcur[key] += (key + 1u < nk ? wst[key + 1u] : nw) - wst[key];
+    __syncthreads();
+    for (unsigned key = tid; key < nk; key += blockDim.x) wst[key] = 0u;
+    __syncthreads();
+  }
+}
+
 template <class SP>
 __device__ __forceinline__ unsigned rec_item(const Rec<SP::S>& r, float* xq) {
   if constexpr (SP::S == 3) {

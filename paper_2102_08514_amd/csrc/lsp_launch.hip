@@ -140,6 +140,26 @@ int place_window_shift(const BinGeom& g) {
   return c;
 }
 
+// The windowed placement with the window's queries in LDS (k_bin_place_winq)
+// for (query, coset) items of splines with M >= 4 cosets, when the window
+// holds two or more records per key on average.
+template <class SP>
+size_t place_winq_lds(const BinGeom& g) {
+  constexpr size_t W = 16384, WQ = W / SP::M + 2;
+  return 4ull * (WQ * SP::S + W + 2ull * g.nkeys);
+}
+
+template <class SP>
+bool place_winq(const BinGeom& g) {
+  if constexpr (!SplitPolicy<SP>::value || SP::M < 4) {
+    return false;
+  } else {
+    if (g.nkeys >= (1u << 17)) return false;
+    if (std::min<long long>(16384, g.tile_items) < 2ll * g.nkeys) return false;
+    return place_winq_lds<SP>(g) <= kLdsMax;
+  }
+}
+
 template <class SP>
 lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws, hipStream_t st) {
   const Bin bn = make_bin<SP>(v, n);
@@ -169,7 +189,13 @@ lsp_status run_schedule(const lsp_vol_s* v, const float* x, int64_t n, void* ws,
       hipLaunchKernelGGL((k_bin_place_win<SP, SPLIT>), dim3(g.tiles), dim3(1024), place_window_lds<SP>(g, cshift),
                          st, v->vol, g, x, hist, start, recs, cshift);
   }
-  if (!cshift)
+  const bool winq = !cshift && place_winq<SP>(g);
+  if constexpr (SPLIT && SP::M >= 4) {
+    if (winq)
+      hipLaunchKernelGGL((k_bin_place_winq<SP>), dim3(g.tiles), dim3(1024), place_winq_lds<SP>(g), st, v->vol, g, x,
+                         hist, start, recs);
+  }
+  if (!cshift && !winq)
     hipLaunchKernelGGL((k_bin_place<SP, SPLIT>), dim3(g.tiles), dim3(1024), lds, st, v->vol, g, x, hist, start,
                        recs);
   return hipGetLastError() == hipSuccess ? LSP_OK : LSP_ERR_HIP;
