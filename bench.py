@@ -264,6 +264,12 @@ def roofline(kernel, n, seconds, bytes_per, flops_per, counters):
     return rec
 
 
+def binned_kernel(w):
+    """Name of the scheduled forward kernel: 4-D units run the variant held to
+    128 VGPRs."""
+    return "k_eval_binned_w4" if w.s == 4 else "k_eval_binned"
+
+
 # ------------------------------------------------------------------ workloads
 class Workload:
     def __init__(self, name, dtype, torch, lsp, W, I):
@@ -333,7 +339,7 @@ def bench_forward(w, steps, warmup, order="sorted", extra=False):
     rec["_eval_s"] = float(pmean[1])
     rec["_bytes_per"] = 4 * w.s + w.info["lookups"] * w.bytes_c + out_b
     rec["_flops_per"] = flops_per_sample(w.info, grad=False)
-    rec["_kernel"] = "k_eval_binned" if order == "sorted" else "k_eval"
+    rec["_kernel"] = binned_kernel(w) if order == "sorted" else "k_eval"
     if extra and order == "sorted":
         k = max(3, steps // 4)
         gw, _, _ = time_phases(lambda marks: step(marks, sched=False), k, 1, torch, nmarks=1)
@@ -476,7 +482,7 @@ def run_workload(name, dtype, args, torch, lsp, W, I, headline=False):
     if "_phases" in r:
         ph = r.pop("_phases")
         n = r["n_samples"]
-        r["roofline"] = {p: roofline({"forward": "k_eval_binned", "backward": "k_adjoint_binned"}[p]
+        r["roofline"] = {p: roofline({"forward": binned_kernel(w), "backward": "k_adjoint_binned"}[p]
                                      if args.order == "sorted" else {"forward": "k_eval_mse",
                                                                      "backward": "k_adjoint"}[p],
                                      n, t, b, fl, counters) for p, (t, b, fl) in ph.items()}
