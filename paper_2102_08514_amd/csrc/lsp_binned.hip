@@ -703,6 +703,100 @@ struct ScatterLds {
   }
 };
 
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Whole-query lanes of a spline with several polynomial pieces run every
+// piece that some lane of the wave needs (the pieces branch on the
+// sub-region).  All pieces' stencil offsets lie in the box [JLO, JHI]^S of
+// FoldedOffsets, so a slot per box position lets the branches share their
+// memory work:
+//   BoxGatherLds loads the box sites before the branch; the compiler drops
+//   the loads of positions that no piece reads, which leaves the union of the
+//   pieces' stencils, loaded once instead of once per piece;
+//   BoxScatterLds only collects each piece's weights in the branch and
+//   converts and adds every position once after it; positions that no piece
+//   writes keep the constant zero and their adds fold away.
+// The values and the fixed-point terms are those of GatherLds / ScatterLds.
+template <class SP, int ESIZE>
+struct Box {
+  using FO = FoldedOffsets<SP, ESIZE>;
+  static constexpr int NJ = FO::NJ, JLO = FO::JLO;
+  static constexpr int N = SP::S == 3 ? NJ * NJ * NJ : NJ * NJ * NJ * NJ;
+  template <int J0, int J1, int J2, int J3>
+  static constexpr int slot() {
+    return (J0 - JLO) + NJ * ((J1 - JLO) + NJ * ((J2 - JLO) + (SP::S == 4 ? NJ * (J3 - JLO) : 0)));
+  }
+  // component d of box position i
+  static constexpr int jc(int i, int d) {
+    for (int e = 0; e < d; ++e) i /= NJ;
+    return i % NJ + JLO;
+  }
+  template <int I>
+  __device__ __forceinline__ static unsigned at(const FO& o) {
+    return o.template at<jc(I, 0), jc(I, 1), jc(I, 2), jc(I, 3)>();
+  }
+};
+
+// multi-piece splines evaluated whole-query per lane
+template <class SP>
+constexpr bool box_pieces() { return SP::K > 1 && !SplitPolicy<SP>::value; }
+
+template <class SP, class AT>
+struct BoxGatherLds {
+  using B = Box<SP, sizeof(AT)>;
+  AT v[B::N];
+  __device__ __forceinline__ void init(const AT* region, const StageInfo<SP, AT>& si, const Folded<SP, AT>& F) {
+    typename B::FO o;
+    o.init(si, F);
+    const char* r = reinterpret_cast<const char*>(region);
+    static_for<B::N>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      v[I] = *reinterpret_cast<const AT*>(r + B::template at<I>(o));
+    });
+  }
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ AT c() const {
+    return v[B::template slot<J0, J1, J2, J3>()];
+  }
+};
+
+template <class SP>
+struct BoxScatterLds {
+  using B = Box<SP, 8>;
+  char* region;
+  typename B::FO o;
+  float gs;
+  float w[B::N];
+  __device__ __forceinline__ void init(unsigned long long* region_, const StageInfo<SP, float>& si,
+                                       const Folded<SP, float>& F, float gscaled) {
+    region = reinterpret_cast<char*>(region_);
+    o.init(si, F);
+    gs = gscaled;
+#pragma unroll
+    for (int i = 0; i < B::N; ++i) w[i] = 0.f;
+  }
+  template <int J0, int J1, int J2, int J3 = 0>
+  __device__ __forceinline__ void put(float wv) {
+    w[B::template slot<J0, J1, J2, J3>()] += wv;
+  }
+  __device__ __forceinline__ void flush() {
+    static_for<B::N>([&](auto ic) {
+      constexpr int I = decltype(ic)::value;
+      if (w[I] != 0.f)
+        atomicAdd(reinterpret_cast<unsigned long long*>(region + B::template at<I>(o)),
+                  static_cast<unsigned long long>(to_fixed(gs * w[I])));
+    });
+  }
+};
+
 // Power-of-two scale 2^shift of a unit's fixed-point region, shift = E - eg
 // with gmax < 2^eg.  |g w| <= gmax (the weights lie in [0, 1]) and a site
 // receives at most one term per item, so every scaled term is below 2^E and
@@ -728,9 +822,15 @@ __device__ __forceinline__ void coset_binned_folded(const Vol& vol, const StageI
     // every item of a unit is stageable (queries outside the brick grid are
     // scheduled apart, under the outlier key); a violation shows as NaN
     if (stageable<SP, AT>(si, F)) {
-      GatherLds<SP, AT> g;
-      g.init(region, si, F);
-      SP::template b_any<AT>(ob, g, b);
+      if constexpr (box_pieces<SP>()) {
+        BoxGatherLds<SP, AT> g;
+        g.init(region, si, F);
+        SP::template b_any<AT>(ob, g, b);
+      } else {
+        GatherLds<SP, AT> g;
+        g.init(region, si, F);
+        SP::template b_any<AT>(ob, g, b);
+      }
     } else {
 #pragma unroll
       for (int m = 0; m < SP::NMON; ++m) b[m] = AT(__builtin_nanf(""));
@@ -1001,9 +1101,16 @@ __device__ __forceinline__ bool adjoint_item(const Vol& vol, const GradVol& gvol
     if constexpr (LDS_G) {
       staged = stageable<SP, float>(si, F);
       if (staged) {
-        ScatterLds<SP> sc;
-        sc.init(lds_g + kk * si.vol, si, F, ldexpf(gq, shift));
-        SP::template w_any<float>(ob, sc, mono);
+        if constexpr (box_pieces<SP>()) {
+          BoxScatterLds<SP> sc;
+          sc.init(lds_g + kk * si.vol, si, F, ldexpf(gq, shift));
+          SP::template w_any<float>(ob, sc, mono);
+          sc.flush();
+        } else {
+          ScatterLds<SP> sc;
+          sc.init(lds_g + kk * si.vol, si, F, ldexpf(gq, shift));
+          SP::template w_any<float>(ob, sc, mono);
+        }
       } else {
         ok = false;
       }
@@ -1020,9 +1127,15 @@ __device__ __forceinline__ bool adjoint_item(const Vol& vol, const GradVol& gvol
       float b[SP::NMON];
       if constexpr (STAGE_C) {
         if (staged) {
-          GatherLds<SP, float> gg;
-          gg.init(lds_c + kk * si.vol, si, F);
-          SP::template b_any<float>(ob, gg, b);
+          if constexpr (box_pieces<SP>()) {
+            BoxGatherLds<SP, float> gg;
+            gg.init(lds_c + kk * si.vol, si, F);
+            SP::template b_any<float>(ob, gg, b);
+          } else {
+            GatherLds<SP, float> gg;
+            gg.init(lds_c + kk * si.vol, si, F);
+            SP::template b_any<float>(ob, gg, b);
+          }
         } else {
 #pragma unroll
           for (int m = 0; m < SP::NMON; ++m) b[m] = __builtin_nanf("");

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 
 #include "../../include/lsp.h"
 #include "lsp_kernels.hip"
