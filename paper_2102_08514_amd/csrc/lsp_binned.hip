@@ -1370,8 +1370,11 @@ __global__ void __launch_bounds__(256) k_adjoint_gather(Vol vol, GradVol gvol, B
           }
           const unsigned unit = brick * g.upb + (SPLIT ? static_cast<unsigned>(k) : 0u);
           const unsigned k0 = unit * g.kpb;
-          if (start[k0] != start[k0 + g.kpb])
-            sum += priv[(static_cast<size_t>(unit) * NC + (SPLIT ? 0 : k)) * vol_r + local];
+          // an empty unit never wrote its slot: load it anyway (its loads
+          // then overlap the emptiness test) and drop the value
+          const bool used = start[k0] != start[k0 + g.kpb];
+          const float v = priv[(static_cast<size_t>(unit) * NC + (SPLIT ? 0 : k)) * vol_r + local];
+          sum += used ? v : 0.f;
         }
   long long off = 0;
 #pragma unroll
