@@ -366,7 +366,10 @@ def bench_mse(w, steps, warmup, order="sorted"):
     loss = torch.zeros(1, device="cuda", dtype=torch.float64)
     f = torch.empty(n, device="cuda")
     dldf = torch.empty(n, device="cuda")
-    gradc = [torch.zeros(c.shape, device="cuda") for c in w.dev]
+    # one buffer for every coset's dL/dc, so clearing it is one fill
+    gflat = torch.zeros(sum(c.numel() for c in w.dev), device="cuda")
+    gradc = list(torch.split(gflat, [c.numel() for c in w.dev]))
+    gradc = [g.view(c.shape) for g, c in zip(gradc, w.dev)]
     gx = torch.empty(n, w.s, device="cuda")
     ws_bytes = Lb.lsp_schedule_size(w.sp.plan, w.vol.handle, n)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
@@ -385,8 +388,7 @@ def bench_mse(w, steps, warmup, order="sorted"):
             Lb.lsp_eval_mse(w.sp.plan, w.vol.handle, x.data_ptr(), y.data_ptr(), n, fo, dldf.data_ptr(),
                             gx.data_ptr(), loss.data_ptr(), w.strm)
         mark(marks, 1)
-        for g in gradc:
-            g.zero_()
+        gflat.zero_()
         if sched:
             Lb.lsp_mse_backward_scheduled(w.sp.plan, w.vol.handle, x.data_ptr(), n, ws.data_ptr(), ws_bytes,
                                           [g.data_ptr() for g in gradc], w.strm)

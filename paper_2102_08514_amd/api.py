@@ -31,6 +31,14 @@ def _check_queries(x, s):
         raise ValueError(f"x must be an N x {s} float32 tensor")
 
 
+def _zero_grad_c(vol, device):
+    """Zeroed float32 arrays shaped like the coset arrays, as views of one
+    buffer (one fill instead of one per coset)."""
+    sizes = [c.numel() for c in vol.coeffs]
+    flat = torch.zeros(sum(sizes), device=device, dtype=torch.float32)
+    return [t.view(c.shape) for t, c in zip(torch.split(flat, sizes), vol.coeffs)]
+
+
 def _check_grad_c(grad_c, vol):
     """grad_c: one float32 array per coset, shaped like the coefficient arrays."""
     if len(grad_c) != len(vol.coeffs):
@@ -184,7 +192,7 @@ class LatticeSpline:
         _require_device(x)
         self._check_sched(schedule, x, vol)
         if grad_c is None:
-            grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
+            grad_c = _zero_grad_c(vol, x.device)
         _check_grad_c(grad_c, vol)
         L.lsp_mse_backward_scheduled(self.plan, vol.handle, x.data_ptr(), x.shape[0], schedule.ws.data_ptr(),
                                      schedule.bytes, [t.data_ptr() for t in grad_c], _stream())
@@ -197,7 +205,7 @@ class LatticeSpline:
         _check_per_query(g, n, "g")
         _require_device(x, g)
         if grad_c is None:
-            grad_c = [torch.zeros(c.shape, device=x.device, dtype=torch.float32) for c in vol.coeffs]
+            grad_c = _zero_grad_c(vol, x.device)
         _check_grad_c(grad_c, vol)
         gx = torch.empty(n, self.s, device=x.device, dtype=torch.float32) if grad_x else None
         if schedule is None:

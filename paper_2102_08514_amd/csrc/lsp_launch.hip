@@ -24,7 +24,7 @@ constexpr size_t kLdsEval = 64 * 1024;    // keep several evaluation workgroups 
 constexpr int kAbsMaxParts = 1024;         // blocks of the max |g| reduction
 constexpr unsigned long long kMinUnits = 1024;        // fewer units than this: smaller bricks
 constexpr unsigned long long kMinEvalGroups = 2048;   // fewer units than this: several workgroups per unit
-constexpr unsigned kScanSingle = 1u << 15;  // key totals scanned by one workgroup up to this count
+constexpr unsigned kScanSingle = 1u << 13;  // key totals scanned by one workgroup up to this count
 constexpr unsigned kOutlierGroups = 128;      // workgroups of the outlier kernels (grid-stride loops)
 // key histogram budget: 3-D bricks stay at 16^3 cells for the big volumes
 // (fewer, fuller bricks amortise the staged halo); 4-D needs the full LDS to
