@@ -495,6 +495,54 @@ def test_scheduled_edge_cases(lsp, name):
     assert float((gxm[: len(X) + 2] - gxf).abs().max()) <= 1e-6 * max(1.0, float(gxf.abs().max()))
 
 
+@pytest.mark.parametrize("name", ["c2", "c4"])
+def test_outlier_key_at_scale(lsp, name):
+    """2^20 queries on the full volume, a third of them pushed up to four
+    cells past a face (some still reaching it with their stencil, some not):
+    those lie outside the brick grid and take the schedule's outlier key and
+    kernels.  The scheduled forward matches the given-order one (the same
+    arithmetic per query), sampled outliers and interior queries match the
+    oracle, and for c4 the scheduled MSE step and fused backward match the
+    given-order MSE head and adjoint."""
+    torch = _torch()
+    cfg = W.get(name)
+    coeffs = I.coefficients(cfg)
+    rng = np.random.default_rng(77)
+    n = 1 << 20
+    ext = cfg.D * (cfg.dims[0] - 1) + 1
+    X = rng.uniform(0.0, ext, (n, cfg.s))
+    out = np.nonzero(rng.random(n) < 1.0 / 3.0)[0]
+    ax = rng.integers(0, cfg.s, len(out))
+    d = rng.uniform(0.0, 4.0 * cfg.D, len(out))
+    X[out, ax] = np.where(rng.random(len(out)) < 0.5, -d, ext + d)
+    X = X.astype(np.float32)
+    sp = lsp.LatticeSpline(cfg.L, cfg.Xi)
+    vol = sp.bind(to_dev(coeffs, torch.float32))
+    x = torch.from_numpy(X).cuda()
+    sch = sp.schedule(vol, x)
+    f0 = sp.eval(vol, x).cpu().numpy()
+    f1 = sp.eval(vol, x, schedule=sch).cpu().numpy()
+    assert np.all(np.isfinite(f1))
+    print(name, "scheduled vs given order", float(np.max(np.abs(f1 - f0))), flush=True)
+    assert normwise(f1, f0.astype(np.float64), coeffs) <= 1e-6
+    idx = np.concatenate([rng.choice(out, 64, replace=False), rng.choice(n, 64, replace=False)])
+    o = ConvolutionSumOracle(cfg.L, cfg.Xi)
+    want = o.eval([c.astype(np.float64) for c in coeffs], X[idx].astype(np.float64))
+    assert normwise(f1[idx], want, coeffs) <= 1e-5
+    if name != "c4":
+        return
+    y = torch.from_numpy(I.targets(cfg, X)).cuda()
+    _, dl0, l0, dx0 = sp.eval_mse(vol, x, y, grad_x=True)
+    _, dl1, l1, dx1 = sp.eval_mse(vol, x, y, schedule=sch, grad_x=True)
+    assert abs(float(l1) - float(l0)) <= 1e-6 * abs(float(l0))
+    assert float((dl1 - dl0).abs().max()) <= 1e-6 * float(dl0.abs().max())
+    assert float((dx1 - dx0).abs().max()) <= 1e-5 * float(dx0.abs().max())
+    gc = sp.mse_backward(vol, x, sch)
+    ga, _ = sp.adjoint(vol, x, dl0)
+    for a, b in zip(gc, ga):
+        assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max())
+
+
 @pytest.mark.parametrize("name", ["c4", "c5", "d4"])
 def test_mse_backward_fused(lsp, name):
     """The fused MSE backward (dL/df kept in the workspace by the scheduled
